@@ -1,0 +1,214 @@
+"""Pins of the solver oracle: smoother, eigenvalue estimate, w-BFBT bounds, FGMRES, exact solutions."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import sympy as sy
+
+from oracle import fem, solver
+from synthetic import WORKLOADS, sinker_centers
+
+X, Y, Z = sy.symbols("x y z")
+
+
+def _cheb_T(m, t):
+    return np.cos(m * np.arccos(t)) if abs(t) <= 1 else np.cosh(m * np.arccosh(abs(t))) * np.sign(t) ** m
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 5])
+def test_chebyshev_matches_scaled_chebyshev_polynomial(degree):
+    lam = np.linspace(0.05, 2.0, 40)
+    A = sp.diags(lam)
+    dinv = np.ones_like(lam)
+    b = np.random.default_rng(0).uniform(-1, 1, lam.size)
+    lmin, lmax = 0.3, 2.2
+    x = solver.chebyshev(A, dinv, b, None, lmin, lmax, degree, x_zero=True)
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    # error e = x - A^-1 b = -p(A) A^-1 b, p(l) = T_d((theta - l)/delta) / T_d(theta/delta)
+    p = np.array([_cheb_T(degree, (theta - l) / delta) for l in lam]) / _cheb_T(degree, theta / delta)
+    assert np.allclose(x, (1.0 - p) * b / lam, rtol=1e-12, atol=1e-13)
+    # and with a non-zero start the error polynomial acts on the initial error
+    x0 = np.random.default_rng(1).uniform(-1, 1, lam.size)
+    x1 = solver.chebyshev(A, dinv, b, x0, lmin, lmax, degree)
+    assert np.allclose(x1 - b / lam, p * (x0 - b / lam), rtol=1e-12, atol=1e-13)
+
+
+def test_lanczos_estimate_is_exact_for_small_spectra():
+    lam = np.array([0.5, 1.0, 3.0, 7.25])
+    A = sp.diags(lam * 2.0)
+    dinv = np.full(4, 0.5)       # D^-1 A = diag(lam)
+    b0 = np.array([1.0, -0.5, 0.25, 0.75])
+    assert abs(solver.lanczos_max(A, dinv, b0, 10) - 7.25) < 1e-12
+    # more steps than the dimension stop at the Krylov breakdown and stay exact
+    big = np.random.default_rng(0).uniform(1, 5, 200)
+    est = solver.lanczos_max(sp.diags(big), np.ones(200), np.ones(200), 10)
+    assert est <= big.max() + 1e-12 and est > 0.9 * big.max()
+
+
+def test_level_schedule():
+    assert solver.level_schedule(32, 2) == [(32, 2), (32, 1), (16, 1), (8, 1), (4, 1)]
+    assert solver.level_schedule(16, 4) == [(16, 4), (16, 2), (16, 1), (8, 1), (4, 1)]
+    assert solver.level_schedule(48, 2)[-1] == (6, 1)
+    assert solver.level_schedule(64, 3) == [(64, 3), (64, 1), (32, 1), (16, 1), (8, 1), (4, 1)]
+    assert solver.level_schedule(4, 2) == [(4, 2), (4, 1)]
+
+
+def _small(N=3, k=2, n=4, a_l=1.0, a_r=1.0, dr=1e4, scale=1.0, seed=1):
+    c = sinker_centers(seed, n)
+    lo, hi = dr ** -0.5, dr ** 0.5
+    return solver.Stokes(N, k, c, 200.0, 0.1, lo * scale, hi * scale, a_l=a_l, a_r=a_r)
+
+
+def _mean_zero_basis(st):
+    P = np.eye(st.np_) - np.outer(st.ones_p, st.ones_p) / st.ones_p.sum()
+    U, s, _ = np.linalg.svd(P)
+    return U[:, : st.np_ - 1]
+
+
+def _wbfbt_spectrum(st):
+    S = st.schur_dense()
+    T = np.column_stack([st.wbfbt_exact(S[:, i]) for i in range(st.np_)])
+    Q = _mean_zero_basis(st)
+    ev = np.linalg.eigvals(Q.T @ T @ Q)
+    return np.sort(ev.real), np.abs(ev.imag).max()
+
+
+@pytest.mark.parametrize("N,k", [(2, 2), (3, 2), (2, 3)])
+def test_wbfbt_lower_bound_when_weights_equal(N, k):
+    # (S_w q, q) <= (S q, q) when C = D: eigenvalues of S_w^-1 S are >= 1, and the bound is sharp
+    st = _small(N, k, a_l=2.0, a_r=2.0)
+    ev, imag = _wbfbt_spectrum(st)
+    assert imag < 1e-8 * ev.max()
+    assert ev[0] >= 1.0 - 1e-10
+    assert ev[0] < 1.5          # observed close to 1 (the bound is nearly attained)
+
+
+def test_wbfbt_invariances():
+    st = _small(3, 2, a_l=1.0, a_r=2.0)
+    r = st.remove_mean(np.random.default_rng(5).uniform(-1, 1, st.np_))
+    z = st.wbfbt_exact(r)
+    # scaling C and D by constants leaves S_w^-1 unchanged (Sec. 3 remark after the lower bound)
+    Cinv, Dinv = st.Cinv.copy(), st.Dinv.copy()
+    st.Cinv, st.Dinv = Cinv / 3.0, Dinv * 7.0
+    st.Kl = (st.B @ sp.diags(st.Cinv) @ st.B.T).tocsr()
+    st.Kr = (st.B @ sp.diags(st.Dinv) @ st.B.T).tocsr()
+    assert np.allclose(st.wbfbt_exact(r), z, rtol=1e-9, atol=1e-12 * np.abs(z).max())
+    # scaling mu by gamma scales S_w^-1 by gamma (so S_w^-1 S is invariant)
+    st2 = _small(3, 2, a_l=1.0, a_r=2.0, scale=10.0)
+    assert np.allclose(st2.wbfbt_exact(r), 10.0 * z, rtol=1e-9, atol=1e-11 * np.abs(z).max())
+
+
+def test_fgmres_two_iterations_with_exact_blocks():
+    w = WORKLOADS["c1"]
+    st = solver.Stokes(w.N, w.k, w.centers(), w.delta, w.omega, w.mu_min, w.mu_max, a_r=w.a_r)
+    cf = sla.cho_factor(st.A.toarray())
+    Spinv = np.linalg.pinv(st.schur_dense())
+
+    def P(x):
+        zp = Spinv @ x[st.nu:]
+        return np.concatenate([sla.cho_solve(cf, x[:st.nu] - st.B.T @ zp), zp])
+
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    x, it, hist = solver.fgmres(st.stokes_matvec, b, P, rtol=1e-10)
+    assert it == 2 and hist[-1] < 1e-12
+
+
+def test_fgmres_history_equals_bruteforce_least_squares():
+    st = _small(2, 2)
+    K = st.stokes_matrix().toarray()
+    b = np.concatenate([st.F, np.random.default_rng(2).uniform(-1, 1, st.np_)])
+    b[st.nu:] = st.remove_mean(b[st.nu:])
+    Dinv = 1.0 / np.concatenate([st.A.diagonal(), np.ones(st.np_)])
+    P = lambda v: Dinv * v
+    _, it, hist = solver.fgmres(lambda v: K @ v, b, P, rtol=1e-14, restart=25, max_iter=25)
+    # brute force: x_j minimizes ||b - K x|| over x in P^-1 K_j(K P^-1, b)
+    M = K * Dinv[None, :]
+    basis = [b / np.linalg.norm(b)]
+    for j in range(1, 13):
+        v = M @ basis[-1]
+        for q in basis:
+            v -= (q @ v) * q
+        for q in basis:
+            v -= (q @ v) * q
+        basis.append(v / np.linalg.norm(v))
+        Vb = np.array(basis[:j]).T
+        y, *_ = np.linalg.lstsq(M @ Vb, b, rcond=None)
+        res = np.linalg.norm(b - M @ Vb @ y) / np.linalg.norm(b)
+        assert abs(res - hist[j]) <= 1e-8 * max(res, 1e-3), j
+
+
+def test_hydrostatic_force_gives_exact_pressure():
+    # f = grad p*, p* = x - 1/2 in P_{k-1}: the discrete solution is u = 0, p = p*
+    m_st = _small(3, 2)
+    m = m_st.mesh
+    fq = np.zeros(m.quad_points().shape)
+    fq[..., 0] = 1.0
+    F = fem.assemble_load(m, fq)[m_st.idx]
+    st = m_st
+    st.F = F
+    u, p = st.direct_solve()
+    assert np.abs(u).max() < 1e-11
+    want = np.zeros(st.np_)
+    for e in range(m.E):
+        want[e * m.n_p] = (m.eidx[e][0] + 0.5) * m.h - 0.5
+        want[e * m.n_p + 1] = m.h / 2                 # mode (1,0,0)
+    assert np.allclose(p, want, atol=1e-11)
+
+
+def test_divergence_free_manufactured_solution_k4():
+    # u* = curl(0, 0, psi) in Q4 cap H^1_0 with div u* = 0, p* = x^3 - 1/4 in P3: exact discrete solution
+    psi = X ** 2 * (1 - X) ** 2 * Y ** 2 * (1 - Y) ** 2 * Z * (1 - Z)
+    u = [sy.diff(psi, Y), -sy.diff(psi, X), sy.Integer(0)]
+    p = X ** 3 - sy.Rational(1, 4)
+    lap = [sum(sy.diff(ui, v, 2) for v in (X, Y, Z)) for ui in u]
+    f = [-lap[i] + sy.diff(p, v) for i, v in enumerate((X, Y, Z))]
+    st = solver.Stokes(2, 4, np.zeros((0, 3)), 200.0, 0.1, 1.0, 1.0,
+                       mu_fn=lambda x: np.ones(x.shape[:-1]),
+                       f_fn=lambda x: np.stack([sy.lambdify((X, Y, Z), fi, "numpy")(
+                           x[..., 0], x[..., 1], x[..., 2]) * np.ones(x.shape[:-1]) for fi in f], -1))
+    uh, ph = st.direct_solve()
+    m = st.mesh
+    ue = np.concatenate([sy.lambdify((X, Y, Z), ui, "numpy")(*m.node_xyz.T) * np.ones(m.n_nodes)
+                         for ui in u])[st.idx]
+    assert np.abs(uh - ue).max() < 1e-9 * np.abs(ue).max()
+    # pressure: element-wise Legendre coefficients of x^3 on [x0, x0 + h]
+    h = m.h
+    for e in range(m.E):
+        x0 = m.eidx[e][0] * h
+        xi = sy.symbols("xi")
+        pe = sy.expand((x0 + h * (xi + 1) / 2) ** 3 - sy.Rational(1, 4))
+        for mi, (a, b, c) in enumerate(m.modes):
+            if b or c:
+                want = 0.0
+            else:
+                La = sy.legendre(a, xi)
+                want = float(sy.integrate(pe * La, (xi, -1, 1)) / sy.integrate(La * La, (xi, -1, 1)))
+            assert abs(ph[e * m.n_p + mi] - want) < 1e-9
+
+
+def test_direct_solution_satisfies_the_saddle_system():
+    st = _small(3, 2, dr=1e6)
+    u, p = st.direct_solve()
+    r1 = st.A @ u + st.B.T @ p - st.F
+    r2 = st.B @ u
+    assert np.linalg.norm(r1) < 1e-10 * np.linalg.norm(st.F)
+    assert np.linalg.norm(r2) < 1e-10 * np.linalg.norm(st.F)
+    assert abs(p[::st.mesh.n_p].mean()) < 1e-14
+
+
+@pytest.mark.slow
+def test_multigrid_preconditioned_solve_converges_to_direct_solution():
+    # FGMRES with V-cycles converges; the iteration count is a range, not a pin (parity unpinned)
+    w = WORKLOADS["c1"]
+    st = solver.Stokes(w.N, w.k, w.centers(), w.delta, w.omega, w.mu_min, w.mu_max, a_r=w.a_r)
+    P = solver.Preconditioner(st)
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    x, it, hist = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-10, max_iter=600)
+    u_ref, p_ref = st.direct_solve()
+    assert np.linalg.norm(x[:st.nu] - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
+    assert np.linalg.norm(st.remove_mean(x[st.nu:]) - p_ref) <= 1e-8 * np.linalg.norm(p_ref)
+    _, it6, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
+    assert 10 <= it6 <= 200
+    # the A sub-solve with one V-cycle: Table 3 reports 18-23 at larger meshes
+    _, ita, _ = solver.fgmres(lambda v: st.A @ v, st.F, P.a_vcycle, rtol=1e-6)
+    assert 5 <= ita <= 30
