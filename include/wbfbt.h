@@ -1,0 +1,194 @@
+/*
+ * wbfbt.h -- C-ABI of the MI355X (gfx950) w-BFBT Stokes library.
+ *
+ * The library implements, with hand-written HIP kernels, the data-parallel hot
+ * path of the weighted-BFBT preconditioned Stokes solver of Rudi, Stadler and
+ * Ghattas, "Weighted BFBT preconditioner for Stokes flow problems with highly
+ * heterogeneous viscosity" (arXiv 1607.03936):
+ *
+ *   -div[mu (grad u + grad u^T)] + grad p = f,   -div u = 0,   u = 0 on the
+ *   boundary of the unit cube (eq. 1), discretized with continuous nodal Q_k
+ *   velocity and discontinuous modal P_{k-1} pressure on a uniform N^3
+ *   hexahedral mesh (Sec. 1.1, eq. 2).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - All vector buffers are DEVICE pointers owned by the caller (for example
+ *    torch tensors' data_ptr()).  Handles (wb_mesh, wb_visc, wb_solver) and
+ *    their internal workspaces are owned by the library.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Apply calls only
+ *    enqueue work and return; wb_visc_*, wb_solver_create and wb_solve
+ *    synchronize the stream.
+ *  - Velocity vectors are [3][n_nodes] (component-major), n_nodes = (kN+1)^3,
+ *    node g = gi + M (gj + M gl), M = kN+1, node (gi, gj, gl) at the
+ *    Gauss-Lobatto-Legendre points of each element.  Values at boundary nodes
+ *    are ignored on input and written as 0 on output (no-slip).
+ *  - Pressure vectors are [E][n_p], E = N^3 elements e = ex + N (ey + N ez),
+ *    n_p = k(k+1)(k+2)/6 Legendre modes L_a(x) L_b(y) L_c(z), a+b+c <= k-1,
+ *    ordered c slowest, then b, then a; mode 0 is the constant.
+ *  - Coefficients at quadrature points are [E][(k+1)^3], Gauss-Legendre
+ *    points q = qx + n (qy + n qz), n = k+1.
+ *  - Every call returns a wb_status; on failure wb_last_error() gives a
+ *    thread-local message.  No partial results are guaranteed on failure.
+ *  - k in {1,2,3,4} for operator applies, k in {2,3,4} for Stokes solves.
+ */
+#ifndef WBFBT_H
+#define WBFBT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WB_API __attribute__((visibility("default")))
+
+typedef enum {
+  WB_OK = 0,
+  WB_EINVAL = 1,        /* bad argument (size, order, NULL handle)           */
+  WB_ENOMEM = 2,        /* device allocation failed                          */
+  WB_EHIP = 3,          /* a HIP runtime call failed                          */
+  WB_ENOCONV = 4,       /* FGMRES reached max_iter before rtol               */
+  WB_ENAN = 5,          /* NaN or Inf met in a reduction                      */
+  WB_EUNSUPPORTED = 6   /* order or option not built                          */
+} wb_status;
+
+typedef enum { WB_FP64 = 0, WB_FP32 = 1, WB_BF16 = 2 } wb_prec;
+
+typedef struct wb_mesh wb_mesh;
+typedef struct wb_visc wb_visc;
+typedef struct wb_solver wb_solver;
+
+/* Solver options.  Defaults (wb_opts_default) follow the paper's settings:
+ * Chebyshev-accelerated point-Jacobi smoothing with 3 pre- and 3 post-steps,
+ * GMRES restarted every 100 iterations, relative residual 1e-6 (Sec. 6-7). */
+typedef struct {
+  double a_l, a_r;        /* Dirichlet boundary amplification of w_l, w_r (eq. 11) */
+  int cheb_degree;        /* Chebyshev-Jacobi steps per smoothing (3)              */
+  int lanczos_steps;      /* CG steps for the largest-eigenvalue estimate (10)     */
+  int restart;            /* FGMRES restart length (100)                           */
+  int max_iter;           /* FGMRES iteration cap (1000)                           */
+  double rtol;            /* ||b - K x|| <= rtol ||b|| (1e-6)                      */
+  int precond_prec;       /* wb_prec of the preconditioner: WB_FP64, WB_FP32 or
+                             WB_BF16 (FP32 with BF16 MFMA contractions)            */
+  int use_learned;        /* 1: learned coarse correction in the velocity V-cycle  */
+  int verbose;            /* 1: print the residual history to stderr              */
+} wb_opts;
+
+typedef struct {
+  int iters;              /* FGMRES iterations                                     */
+  double rel_res;         /* final true relative residual ||b - K x|| / ||b||      */
+  double t_setup_s;       /* wall time of wb_solver_create                         */
+  double t_solve_s;       /* wall time of the last wb_solve                        */
+  int fell_back;          /* learned correction rejected in favour of the V-cycle  */
+  int learned_used;       /* learned correction applications that were accepted    */
+  size_t device_bytes;    /* device memory held by the solver                      */
+} wb_report;
+
+WB_API void wb_opts_default(wb_opts* o);
+WB_API const char* wb_last_error(void);
+
+/* ---- mesh (Sec. 1.1): uniform N^3 hexahedra of the unit cube, order k ---- */
+/* N >= 1, 1 <= k <= 4.  Creates structured metadata only (no device memory). */
+WB_API wb_status wb_mesh_create(int N, int k, wb_mesh** out);
+WB_API void wb_mesh_destroy(wb_mesh* m);
+/* n_nodes = (kN+1)^3, n_elem = N^3, n_p = k(k+1)(k+2)/6. Any output may be NULL. */
+WB_API wb_status wb_mesh_sizes(const wb_mesh* m, long long* n_nodes, long long* n_elem, int* n_p);
+
+/* ---- viscosity (Sec. 2.1, multi-sinker benchmark) ----
+ * mu(x) = (mu_max - mu_min)(1 - chi(x)) + mu_min,
+ * chi(x) = prod_i [1 - exp(-delta max(0, |c_i - x| - omega/2)^2)].
+ * centers_host: [n_sinkers][3] HOST doubles in (0,1)^3 (n_sinkers >= 0).
+ * Evaluates mu at every element's Gauss points and at the velocity nodes. */
+WB_API wb_status wb_visc_create_sinker(const wb_mesh* m, const double* centers_host, int n_sinkers,
+                                       double delta, double omega, double mu_min, double mu_max,
+                                       void* stream, wb_visc** out);
+/* A viscosity given by its values: mu_q_dev [E][(k+1)^3] at the Gauss points and
+ * mu_nodes_dev [n_nodes] at the velocity nodes, both DEVICE, copied in. */
+WB_API wb_status wb_visc_create_values(const wb_mesh* m, const double* mu_q_dev,
+                                       const double* mu_nodes_dev, void* stream, wb_visc** out);
+/* Copies the stored values out (either pointer may be NULL). */
+WB_API wb_status wb_visc_values(const wb_visc* v, double* mu_q_dev, double* mu_nodes_dev, void* stream);
+WB_API void wb_visc_destroy(wb_visc* v);
+
+/* ---- right-hand side (Sec. 2.1): f = (0, 0, beta (chi - 1)) ----
+ * F_i = sum over elements of the Gauss-quadrature integral of f . phi_i;
+ * f_dev: [3][n_nodes] DEVICE, overwritten (boundary entries 0). */
+WB_API wb_status wb_rhs_sinker(const wb_mesh* m, const double* centers_host, int n_sinkers,
+                               double delta, double omega, double beta, double* f_dev, void* stream);
+
+/* ---- discrete operators of eq. (2), matrix-free ----
+ * A: viscous stress, (A u)_i = sum_e int_e 2 mu eps(u) : eps(phi_i)   (Sec. 1.1, 3.1)
+ * B: divergence, (B u)_{e,m} = -int_e psi_m div u  (B = -div, Sec. 3.1)
+ * B^T: gradient, (B^T p)_i = -sum_e int_e p div phi_i
+ * u, y: [3][n_nodes]; p: [E][n_p].  Outputs are overwritten.  In-place (u == y) is not allowed. */
+WB_API wb_status wb_apply_A(const wb_mesh* m, const wb_visc* v, const double* u, double* y, void* stream);
+WB_API wb_status wb_apply_B(const wb_mesh* m, const double* u, double* p, void* stream);
+WB_API wb_status wb_apply_BT(const wb_mesh* m, const double* p, double* u, void* stream);
+/* Fused Stokes operator of eq. (2): yu = A u + B^T p, yp = B u (one kernel). */
+WB_API wb_status wb_apply_stokes(const wb_mesh* m, const wb_visc* v, const double* u, const double* p,
+                                 double* yu, double* yp, void* stream);
+/* Reduced-precision A apply: FP32 buffers; prec = WB_FP32 (FP32 arithmetic) or
+ * WB_BF16 (BF16 MFMA contractions accumulated in FP32). */
+WB_API wb_status wb_apply_A_lowp(const wb_mesh* m, const wb_visc* v, int prec, const float* u,
+                                 float* y, void* stream);
+
+/* ---- solver: w-BFBT (eq. 7, 11) + p/h-multigrid (Sec. 6) + FGMRES (eq. 3) ----
+ * Builds the velocity multigrid hierarchy, the weights C = M(w_l), D = M(w_r),
+ * w = a sqrt(mu), the two pressure-Poisson hierarchies and the Krylov space.
+ * opts may be NULL (defaults).  Synchronizes `stream`. */
+WB_API wb_status wb_solver_create(const wb_mesh* m, const wb_visc* v, const wb_opts* opts,
+                                  void* stream, wb_solver** out);
+WB_API void wb_solver_destroy(wb_solver* s);
+
+/* z = S_w^-1 r: K_l^-1 (B C^-1 A D^-1 B^T) K_r^-1 r with each K^-1 one
+ * V-cycle (eq. 7); r, z: [E][n_p] FP64; the output has zero mean. */
+WB_API wb_status wb_apply_wbfbt(wb_solver* s, const double* r, double* z, void* stream);
+/* z = (one V-cycle of A) r, Sec. 6; r, z: [3][n_nodes]. */
+WB_API wb_status wb_apply_vcycle_A(wb_solver* s, const double* r, double* z, void* stream);
+/* K_w = B D_w^-1 B^T with w the left (side 0) or right (side 1) weight (eq. 7). */
+WB_API wb_status wb_apply_K(wb_solver* s, int side, const double* p, double* y, void* stream);
+/* z = (one K_w V-cycle) r: discontinuous smoothing, Q_k Poisson V-cycle with
+ * coefficient 1/w (eq. 9-10, Sec. 6), smoothing, mean removal. */
+WB_API wb_status wb_apply_vcycle_K(wb_solver* s, int side, const double* r, double* z, void* stream);
+/* Upper block-triangular preconditioner of eq. (3):
+ * z_p = S_w^-1 r_p, z_u = (A V-cycle)(r_u - B^T z_p). */
+WB_API wb_status wb_apply_precond(wb_solver* s, const double* r_u, const double* r_p,
+                                  double* z_u, double* z_p, void* stream);
+/* FGMRES(restart), right-preconditioned, x0 = 0, on K [u; p] = [f; 0].
+ * f: [3][n_nodes]; u, p: outputs (p has zero mean).  rep may be NULL.
+ * Returns WB_ENOCONV if max_iter is reached (u, p hold the last iterate). */
+WB_API wb_status wb_solve(wb_solver* s, const double* f, double* u, double* p, wb_report* rep,
+                          void* stream);
+
+/* Inspection of setup products (for tests).  what:
+ *   0 C^-1 per node [n_nodes]          1 D^-1 per node [n_nodes]
+ *   2 inverse Jacobi diagonal of A at `level` [3][n_nodes(level)]
+ *   3 coarsened viscosity at `level` [E(level)][(k(level)+1)^3]
+ *   4 inverse diagonal of K_l [E][n_p]  5 inverse diagonal of K_r [E][n_p]
+ *   6 Poisson coefficient 1/w_l at `level`, 7 same for 1/w_r
+ *   8 inverse Jacobi diagonal of the left Poisson operator at `level`
+ * out_dev: DEVICE FP64 buffer of the stated size. */
+WB_API wb_status wb_solver_query(wb_solver* s, int what, int level, double* out_dev, void* stream);
+/* Hierarchy description: which = 0 velocity, 1 left Poisson, 2 right Poisson,
+ * 3 discontinuous K levels (nlevels = 2: left, right).  Arrays of length >= 16;
+ * lmax[l] is the Chebyshev upper bound (1.1 x the Lanczos estimate), 0 on the coarsest. */
+WB_API wb_status wb_solver_levels(wb_solver* s, int which, int* nlevels, int* Ns, int* ks, double* lmax);
+
+/* ---- learned coarse correction (velocity V-cycle, level Q1 on N/2) ----
+ * A small FP32 3D convolutional network N_theta maps (log10 mu_c, r_c/|r_c|) on
+ * the coarse node grid to e_c/|r_c|.  Training pairs (r_c, A_c^-1 r_c) are
+ * generated by the library on the seeded sinker fields given; training runs
+ * on the GPU with the library's own forward/backward kernels and Adam. */
+WB_API wb_status wb_learned_train(wb_solver* s, const double* centers_host, const int* n_sinkers,
+                                  int n_fields, int pairs_per_field, int epochs, double lr,
+                                  double* final_loss, void* stream);
+/* Flat FP32 parameter blob: query size with params == NULL. HOST pointers. */
+WB_API wb_status wb_learned_get(wb_solver* s, float* params, long long* n_params);
+WB_API wb_status wb_learned_set(wb_solver* s, const float* params, long long n_params);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WBFBT_H */

@@ -152,14 +152,15 @@ class Mesh:
     def p_dof(self):
         return self.E * self.n_p
 
-    def quad_points(self):
-        """Physical Gauss points, [E, n^3, 3]."""
+    def quad_points(self, elements=None):
+        """Physical Gauss points, [E, n^3, 3] (or of the given elements only)."""
         xg, _ = gauss_rule(self.n)
         n = self.n
         qa, qb, qc = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
         qa, qb, qc = (v.transpose(2, 1, 0).ravel() for v in (qa, qb, qc))
         loc = np.stack([xg[qa], xg[qb], xg[qc]], axis=1)                     # [n^3, 3]
-        return (self.eidx[:, None, :] + 0.5 * (loc[None, :, :] + 1.0)) * self.h
+        eidx = self.eidx if elements is None else self.eidx[np.asarray(elements)]
+        return (eidx[:, None, :] + 0.5 * (loc[None, :, :] + 1.0)) * self.h
 
 
 # ----------------------------------------------------------------------------
@@ -404,3 +405,35 @@ def coarsen_coefficient_h(coef_q: np.ndarray, Nf: int, n: int) -> np.ndarray:
     f = f.reshape(Nc ** 3, (2 * n) ** 3)
     out = f @ kron3(Q, Q, Q).T
     return np.maximum(out, f.min(axis=1, keepdims=True))
+
+
+# ----------------------------------------------------------------------------
+# Row-wise evaluation for large meshes (sampled parity checks)
+# ----------------------------------------------------------------------------
+
+def elements_of_node(mesh: Mesh, g: int):
+    """Elements whose closure contains global node g."""
+    M, k, N = mesh.M, mesh.k, mesh.N
+    idx = (g % M, (g // M) % M, g // (M * M))
+    cand = []
+    for gi in idx:
+        c = {gi // k} if gi % k else {gi // k - 1, gi // k}
+        cand.append(sorted(e for e in c if 0 <= e < N))
+    return [ex + N * (ey + N * ez) for ez in cand[2] for ey in cand[1] for ex in cand[0]]
+
+
+def apply_A_rows(mesh: Mesh, mu_q_of, u: np.ndarray, dofs) -> np.ndarray:
+    """(A u)_i for the velocity DOFs i = c * n_nodes + g, by element sums (no assembly).
+
+    mu_q_of(elements) -> [len(elements), n^3] viscosity at those elements' Gauss points."""
+    out = np.zeros(len(dofs))
+    nn = mesh.n_nodes
+    for r, dof in enumerate(dofs):
+        c, g = divmod(int(dof), nn)
+        els = elements_of_node(mesh, g)
+        Ae = element_viscous(mesh.k, mesh.h, mu_q_of(np.array(els)))
+        for t, e in enumerate(els):
+            loc = int(np.flatnonzero(mesh.elem_nodes[e] == g)[0])
+            gd = np.concatenate([cc * nn + mesh.elem_nodes[e] for cc in range(3)])
+            out[r] += Ae[t, c * mesh.n ** 3 + loc] @ u[gd]
+    return out

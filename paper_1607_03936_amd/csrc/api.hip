@@ -1,0 +1,456 @@
+// C-ABI entry points (declared in include/wbfbt.h).  Every call converts internal
+// exceptions into a wb_status and a thread-local message.
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "solver.h"
+
+namespace wb {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+template <typename F>
+wb_status guard(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return WB_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return WB_EINVAL;
+  }
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{WB_EHIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+Mesh make_mesh(int N, int k) {
+  WB_REQUIRE(N >= 1 && N <= 1024, WB_EINVAL, "N must be in [1, 1024]");
+  WB_REQUIRE(k >= 1 && k <= 4, WB_EUNSUPPORTED, "k must be in [1, 4]");
+  Mesh m;
+  m.N = N;
+  m.k = k;
+  m.n = k + 1;
+  m.M = k * N + 1;
+  const long long nn = (long long)m.M * m.M * m.M;
+  WB_REQUIRE(3 * nn < (1LL << 31), WB_EINVAL, "mesh too large for 32-bit node indices");
+  m.nn = (int)nn;
+  m.E = N * N * N;
+  m.np = modes(k, nullptr, nullptr, nullptr);
+  m.h = 1.0 / N;
+  return m;
+}
+
+std::vector<double> node_coords_1d(const Mesh& m) {
+  const Tables& t = tables(m.k);
+  std::vector<double> x1(m.M);
+  for (int e = 0; e < m.N; ++e)
+    for (int a = 0; a <= m.k; ++a) x1[e * m.k + a] = (e + 0.5 * (t.xl[a] + 1.0)) / m.N;
+  x1[m.M - 1] = 1.0;
+  return x1;
+}
+
+}  // namespace
+}  // namespace wb
+
+using namespace wb;
+
+extern "C" {
+
+void wb_opts_default(wb_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->a_l = 1.0;
+  o->a_r = 1.0;
+  o->cheb_degree = 3;
+  o->lanczos_steps = 10;
+  o->restart = 100;
+  o->max_iter = 1000;
+  o->rtol = 1e-6;
+  o->precond_prec = WB_FP64;
+  o->use_learned = 0;
+  o->verbose = 0;
+}
+
+const char* wb_last_error(void) { return g_err.c_str(); }
+
+wb_status wb_mesh_create(int N, int k, wb_mesh** out) {
+  return guard([&] {
+    WB_REQUIRE(out, WB_EINVAL, "out is NULL");
+    std::unique_ptr<wb_mesh> m(new wb_mesh());
+    m->m = make_mesh(N, k);
+    *out = m.release();
+    return WB_OK;
+  });
+}
+
+void wb_mesh_destroy(wb_mesh* m) { delete m; }
+
+wb_status wb_mesh_sizes(const wb_mesh* m, long long* n_nodes, long long* n_elem, int* n_p) {
+  return guard([&] {
+    WB_REQUIRE(m, WB_EINVAL, "mesh is NULL");
+    if (n_nodes) *n_nodes = m->m.nn;
+    if (n_elem) *n_elem = m->m.E;
+    if (n_p) *n_p = m->m.np;
+    return WB_OK;
+  });
+}
+
+wb_status wb_visc_create_sinker(const wb_mesh* mh, const double* centers, int ns, double delta,
+                                double omega, double mu_min, double mu_max, void* stream,
+                                wb_visc** out) {
+  return guard([&] {
+    WB_REQUIRE(mh && out, WB_EINVAL, "NULL argument");
+    WB_REQUIRE(ns >= 0 && (ns == 0 || centers), WB_EINVAL, "bad sinker centres");
+    WB_REQUIRE(mu_min > 0 && mu_max >= mu_min && delta > 0 && omega >= 0, WB_EINVAL,
+               "bad sinker parameters");
+    const Mesh& m = mh->m;
+    hipStream_t st = S(stream);
+    std::unique_ptr<wb_visc> v(new wb_visc());
+    v->m = m;
+    const size_t nq = (size_t)m.E * m.n * m.n * m.n;
+    WB_HIP(hipMalloc(&v->mu_q, sizeof(double) * nq));
+    WB_HIP(hipMalloc(&v->mu_nodes, sizeof(double) * m.nn));
+    double* dc = nullptr;
+    double* dx = nullptr;
+    WB_HIP(hipMalloc(&dc, sizeof(double) * 3 * (ns > 0 ? ns : 1)));
+    WB_HIP(hipMalloc(&dx, sizeof(double) * m.M));
+    auto x1 = node_coords_1d(m);
+    if (ns > 0) WB_HIP(hipMemcpy(dc, centers, sizeof(double) * 3 * ns, hipMemcpyHostToDevice));
+    WB_HIP(hipMemcpy(dx, x1.data(), sizeof(double) * m.M, hipMemcpyHostToDevice));
+    launch_sinker_q(st, m.N, m.k, dc, ns, delta, omega, mu_min, mu_max, 0.0, v->mu_q, nullptr);
+    launch_sinker_nodes(st, m.N, m.k, dx, dc, ns, delta, omega, mu_min, mu_max, v->mu_nodes);
+    check_launch();
+    WB_HIP(hipStreamSynchronize(st));
+    (void)hipFree(dc);
+    (void)hipFree(dx);
+    *out = v.release();
+    return WB_OK;
+  });
+}
+
+wb_status wb_visc_create_values(const wb_mesh* mh, const double* mu_q, const double* mu_nodes,
+                                void* stream, wb_visc** out) {
+  return guard([&] {
+    WB_REQUIRE(mh && out && mu_q && mu_nodes, WB_EINVAL, "NULL argument");
+    const Mesh& m = mh->m;
+    hipStream_t st = S(stream);
+    std::unique_ptr<wb_visc> v(new wb_visc());
+    v->m = m;
+    const size_t nq = (size_t)m.E * m.n * m.n * m.n;
+    WB_HIP(hipMalloc(&v->mu_q, sizeof(double) * nq));
+    WB_HIP(hipMalloc(&v->mu_nodes, sizeof(double) * m.nn));
+    WB_HIP(hipMemcpyAsync(v->mu_q, mu_q, sizeof(double) * nq, hipMemcpyDeviceToDevice, st));
+    WB_HIP(hipMemcpyAsync(v->mu_nodes, mu_nodes, sizeof(double) * m.nn, hipMemcpyDeviceToDevice, st));
+    WB_HIP(hipStreamSynchronize(st));
+    *out = v.release();
+    return WB_OK;
+  });
+}
+
+wb_status wb_visc_values(const wb_visc* v, double* mu_q, double* mu_nodes, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(v, WB_EINVAL, "visc is NULL");
+    hipStream_t st = S(stream);
+    const Mesh& m = v->m;
+    if (mu_q)
+      WB_HIP(hipMemcpyAsync(mu_q, v->mu_q, sizeof(double) * m.E * m.n * m.n * m.n,
+                            hipMemcpyDeviceToDevice, st));
+    if (mu_nodes)
+      WB_HIP(hipMemcpyAsync(mu_nodes, v->mu_nodes, sizeof(double) * m.nn, hipMemcpyDeviceToDevice, st));
+    WB_HIP(hipStreamSynchronize(st));
+    return WB_OK;
+  });
+}
+
+void wb_visc_destroy(wb_visc* v) {
+  if (!v) return;
+  (void)hipFree(v->mu_q);
+  (void)hipFree(v->mu_nodes);
+  if (v->mu_q_f) (void)hipFree(v->mu_q_f);
+  delete v;
+}
+
+wb_status wb_rhs_sinker(const wb_mesh* mh, const double* centers, int ns, double delta,
+                        double omega, double beta, double* f, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && f, WB_EINVAL, "NULL argument");
+    WB_REQUIRE(ns >= 0 && (ns == 0 || centers), WB_EINVAL, "bad sinker centres");
+    const Mesh& m = mh->m;
+    hipStream_t st = S(stream);
+    const size_t nq = (size_t)m.E * m.n * m.n * m.n;
+    double *fq = nullptr, *dc = nullptr;
+    WB_HIP(hipMalloc(&fq, sizeof(double) * nq));
+    WB_HIP(hipMalloc(&dc, sizeof(double) * 3 * (ns > 0 ? ns : 1)));
+    if (ns > 0) WB_HIP(hipMemcpy(dc, centers, sizeof(double) * 3 * ns, hipMemcpyHostToDevice));
+    launch_sinker_q(st, m.N, m.k, dc, ns, delta, omega, 1.0, 1.0, beta, nullptr, fq);
+    launch_fill<double>(st, f, 0.0, (size_t)3 * m.nn);
+    launch_load(st, m.N, m.k, fq, f);
+    check_launch();
+    WB_HIP(hipStreamSynchronize(st));
+    (void)hipFree(fq);
+    (void)hipFree(dc);
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_A(const wb_mesh* mh, const wb_visc* v, const double* u, double* y, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && v && u && y, WB_EINVAL, "NULL argument");
+    WB_REQUIRE(u != y, WB_EINVAL, "in-place apply is not allowed");
+    const Mesh& m = mh->m;
+    launch_fill<double>(S(stream), y, 0.0, (size_t)3 * m.nn);
+    launch_op<double>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q, nullptr, nullptr, nullptr,
+                      nullptr);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_B(const wb_mesh* mh, const double* u, double* p, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && u && p, WB_EINVAL, "NULL argument");
+    const Mesh& m = mh->m;
+    WB_REQUIRE(m.k >= 2, WB_EUNSUPPORTED, "B needs k >= 2");
+    launch_op<double>(S(stream), F_B | F_DIR, 3, m.N, m.k, u, nullptr, nullptr, nullptr, p, nullptr,
+                      nullptr);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_BT(const wb_mesh* mh, const double* p, double* u, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && u && p, WB_EINVAL, "NULL argument");
+    const Mesh& m = mh->m;
+    WB_REQUIRE(m.k >= 2, WB_EUNSUPPORTED, "B^T needs k >= 2");
+    launch_fill<double>(S(stream), u, 0.0, (size_t)3 * m.nn);
+    launch_op<double>(S(stream), F_BT | F_DIR, 3, m.N, m.k, nullptr, u, nullptr, p, nullptr, nullptr,
+                      nullptr);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_stokes(const wb_mesh* mh, const wb_visc* v, const double* u, const double* p,
+                          double* yu, double* yp, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && v && u && p && yu && yp, WB_EINVAL, "NULL argument");
+    WB_REQUIRE(u != yu, WB_EINVAL, "in-place apply is not allowed");
+    const Mesh& m = mh->m;
+    WB_REQUIRE(m.k >= 2, WB_EUNSUPPORTED, "Stokes operator needs k >= 2");
+    launch_fill<double>(S(stream), yu, 0.0, (size_t)3 * m.nn);
+    launch_op<double>(S(stream), F_A | F_BT | F_B | F_DIR, 3, m.N, m.k, u, yu, v->mu_q, p, yp, nullptr,
+                      nullptr);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_A_lowp(const wb_mesh* mh, const wb_visc* vc, int prec, const float* u, float* y,
+                          void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && vc && u && y, WB_EINVAL, "NULL argument");
+    WB_REQUIRE(u != y, WB_EINVAL, "in-place apply is not allowed");
+    WB_REQUIRE(prec == WB_FP32, WB_EUNSUPPORTED, "precision not built");
+    const Mesh& m = mh->m;
+    wb_visc* v = const_cast<wb_visc*>(vc);
+    const size_t nq = (size_t)m.E * m.n * m.n * m.n;
+    if (!v->mu_q_f) {
+      WB_HIP(hipMalloc(&v->mu_q_f, sizeof(float) * nq));
+      launch_cast<double, float>(S(stream), nq, v->mu_q, v->mu_q_f);
+    }
+    launch_fill<float>(S(stream), y, 0.0f, (size_t)3 * m.nn);
+    launch_op<float>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q_f, nullptr, nullptr, nullptr,
+                     nullptr);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_solver_create(const wb_mesh* mh, const wb_visc* v, const wb_opts* opts, void* stream,
+                           wb_solver** out) {
+  return guard([&] {
+    WB_REQUIRE(mh && v && out, WB_EINVAL, "NULL argument");
+    wb_opts o;
+    if (opts) o = *opts;
+    else wb_opts_default(&o);
+    Solver* s = solver_create(mh->m, v->mu_q, v->mu_nodes, o, S(stream));
+    check_launch();
+    *out = reinterpret_cast<wb_solver*>(s);
+    return WB_OK;
+  });
+}
+
+void wb_solver_destroy(wb_solver* s) { delete reinterpret_cast<Solver*>(s); }
+
+static Solver& SV(wb_solver* s) {
+  WB_REQUIRE(s, WB_EINVAL, "solver is NULL");
+  return *reinterpret_cast<Solver*>(s);
+}
+
+wb_status wb_apply_wbfbt(wb_solver* sh, const double* r, double* z, void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(r && z && r != z, WB_EINVAL, "bad vectors");
+    s.st = S(stream);
+    apply_wbfbt<double>(s, *s.pd, r, z);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_vcycle_A(wb_solver* sh, const double* r, double* z, void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(r && z && r != z, WB_EINVAL, "bad vectors");
+    s.st = S(stream);
+    apply_vcycle_A<double>(s, *s.pd, r, z);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_K(wb_solver* sh, int side, const double* p, double* y, void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(side == 0 || side == 1, WB_EINVAL, "side must be 0 (left) or 1 (right)");
+    WB_REQUIRE(p && y && p != y, WB_EINVAL, "bad vectors");
+    s.st = S(stream);
+    apply_K<double>(s, *s.pd, side, p, y);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_vcycle_K(wb_solver* sh, int side, const double* r, double* z, void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(side == 0 || side == 1, WB_EINVAL, "side must be 0 (left) or 1 (right)");
+    WB_REQUIRE(r && z && r != z, WB_EINVAL, "bad vectors");
+    s.st = S(stream);
+    apply_vcycle_K<double>(s, *s.pd, side, r, z);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_precond(wb_solver* sh, const double* ru, const double* rp, double* zu, double* zp,
+                           void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(ru && rp && zu && zp, WB_EINVAL, "bad vectors");
+    s.st = S(stream);
+    apply_precond_any(s, ru, rp, zu, zp);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_solve(wb_solver* sh, const double* f, double* u, double* p, wb_report* rep,
+                   void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(f && u && p, WB_EINVAL, "bad vectors");
+    s.st = S(stream);
+    wb_status r = fgmres(s, f, u, p, rep);
+    check_launch();
+    if (r == WB_ENOCONV) set_error("FGMRES reached max_iter before rtol");
+    return r;
+  });
+}
+
+wb_status wb_solver_query(wb_solver* sh, int what, int level, double* out, void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(out, WB_EINVAL, "out is NULL");
+    hipStream_t st = S(stream);
+    Precond<double>& P = *s.pd;
+    const Mesh& m = s.m;
+    auto cp = [&](const double* src, size_t n) {
+      WB_HIP(hipMemcpyAsync(out, src, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    };
+    auto lev = [&](Hierarchy<double>& H) -> Level<double>& {
+      WB_REQUIRE(level >= 0 && level < (int)H.L.size(), WB_EINVAL, "level out of range");
+      return H.L[level];
+    };
+    switch (what) {
+      case 0: cp(P.winv[0], m.nn); break;
+      case 1: cp(P.winv[1], m.nn); break;
+      case 2: { auto& L = lev(P.A); cp(L.dinv, L.len); } break;
+      case 3: { auto& L = lev(P.A); cp(L.coef, (size_t)L.E * (L.k + 1) * (L.k + 1) * (L.k + 1)); } break;
+      case 4: cp(P.dk[0], (size_t)m.E * m.np); break;
+      case 5: cp(P.dk[1], (size_t)m.E * m.np); break;
+      case 6: { auto& L = lev(P.Pois[0]); cp(L.coef, (size_t)L.E * (L.k + 1) * (L.k + 1) * (L.k + 1)); } break;
+      case 7: { auto& L = lev(P.Pois[1]); cp(L.coef, (size_t)L.E * (L.k + 1) * (L.k + 1) * (L.k + 1)); } break;
+      case 8: { auto& L = lev(P.Pois[0]); cp(L.dinv, L.len); } break;
+      default: throw Error{WB_EINVAL, "unknown query"};
+    }
+    WB_HIP(hipStreamSynchronize(st));
+    return WB_OK;
+  });
+}
+
+wb_status wb_solver_levels(wb_solver* sh, int which, int* nlevels, int* Ns, int* ks, double* lmax) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    Precond<double>& P = *s.pd;
+    if (which == 3) {
+      if (nlevels) *nlevels = 2;
+      for (int i = 0; i < 2; ++i) {
+        if (Ns) Ns[i] = s.m.N;
+        if (ks) ks[i] = s.m.k;
+        if (lmax) lmax[i] = P.klmax[i];
+      }
+      return WB_OK;
+    }
+    WB_REQUIRE(which >= 0 && which <= 2, WB_EINVAL, "which must be 0..3");
+    Hierarchy<double>& H = which == 0 ? P.A : P.Pois[which - 1];
+    const int nl = (int)H.L.size();
+    if (nlevels) *nlevels = nl;
+    for (int i = 0; i < nl && i < 16; ++i) {
+      if (Ns) Ns[i] = H.L[i].N;
+      if (ks) ks[i] = H.L[i].k;
+      if (lmax) lmax[i] = H.L[i].lmax;
+    }
+    return WB_OK;
+  });
+}
+
+wb_status wb_learned_train(wb_solver* sh, const double*, const int*, int, int, int, double, double*,
+                           void*) {
+  return guard([&] {
+    (void)SV(sh);
+    throw Error{WB_EUNSUPPORTED, "learned coarse correction not built"};
+    return WB_OK;
+  });
+}
+wb_status wb_learned_get(wb_solver* sh, float*, long long*) {
+  return guard([&] {
+    (void)SV(sh);
+    throw Error{WB_EUNSUPPORTED, "learned coarse correction not built"};
+    return WB_OK;
+  });
+}
+wb_status wb_learned_set(wb_solver* sh, const float*, long long) {
+  return guard([&] {
+    (void)SV(sh);
+    throw Error{WB_EUNSUPPORTED, "learned coarse correction not built"};
+    return WB_OK;
+  });
+}
+
+}  // extern "C"

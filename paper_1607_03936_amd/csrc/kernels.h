@@ -1,0 +1,113 @@
+// Launchers of the HIP kernels (host side).  All launches go to `st`.
+#pragma once
+
+#include "wb_internal.h"
+
+namespace wb {
+
+// Operator flags: viscous/Poisson stiffness, gradient B^T p, divergence B u, Dirichlet mask.
+enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8 };
+
+// Sum-factorized element operator on a level with N elements/dir and order k.
+// NC = 3 (viscous stress, coef = mu) or 1 (scalar Poisson, coef = c).
+//   y   += op(u)   (y must be zeroed by the caller; atomics)       [NC][nn]
+//   pout = B u     (written)                                         [E][np]
+//   sin: optional per-node input scaling, sout: optional per-node output scaling.
+template <typename T>
+void launch_op(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
+               const T* pin, T* pout, const T* sin, const T* sout);
+
+// Jacobi diagonal (not inverted) of the NC-component operator, accumulated into diag (zeroed).
+void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* coef, double* diag);
+// dinv = 1/diag, 1 on Dirichlet nodes (if dir).
+void launch_invert_diag(hipStream_t st, int NC, int N, int k, bool dir, double* d);
+
+// Lumped sqrt(mu)-weighted GLL mass with amplification `amp` on boundary elements (eq. 7, 11):
+// accumulated into cnodes (zeroed), [nn].
+void launch_lumped_mass(hipStream_t st, int N, int k, double amp, const double* mu_nodes,
+                        double* cnodes);
+// dinvK[e*np+m] = 1 / sum_{c,i interior} (B_e[m,(c,i)])^2 dinv_nodes[g(e,i)]
+void launch_diag_K(hipStream_t st, int N, int k, const double* bhat, const double* dinv_nodes,
+                   double* dinvK);
+
+// Multi-sinker viscosity at Gauss points (mu_q) and/or body-force z-component (f_q),
+// and at the velocity nodes.
+void launch_sinker_q(hipStream_t st, int N, int k, const double* centers, int ns, double delta,
+                     double omega, double mu_min, double mu_max, double beta, double* mu_q,
+                     double* f_q);
+void launch_sinker_nodes(hipStream_t st, int N, int k, const double* x1, const double* centers,
+                         int ns, double delta, double omega, double mu_min, double mu_max,
+                         double* mu_nodes);
+// F_z += int f_z phi_i  (F zeroed by the caller), boundary entries untouched (0).
+void launch_load(hipStream_t st, int N, int k, const double* f_q, double* F);
+// Coefficient transforms at the Gauss points: c = scale / (amp_e sqrt(mu)) with amp_e on
+// boundary elements (Poisson coefficient 1/w of eq. 9-11) or a plain FP64->FP32 cast.
+void launch_poisson_coef(hipStream_t st, int N, int k, double amp, const double* mu_q, double* c_q);
+
+// Transfers: tensor product of a 1D sparse matrix (rows: cnt / col / val, width W).
+struct Rows1D {
+  int rows, cols, W;
+  int* cnt;
+  int* col;
+  double* val;
+};
+template <typename T>
+void launch_kron(hipStream_t st, const Rows1D& R, int NC, bool dir, bool add, const T* in, T* out);
+
+// Element-wise L2 projection Q_k -> P_{k-1} (gather) and its transpose (scatter-add).
+template <typename T>
+void launch_modal_I(hipStream_t st, int N, int k, const T* u, T* p, bool add);
+template <typename T>
+void launch_modal_IT(hipStream_t st, int N, int k, const T* p, T* u);
+
+// L2 adjoint of element-wise interpolation of a coefficient at Gauss points (clamped below by
+// the local fine minimum): p-coarsening (same mesh) and h-coarsening (2:1).
+void launch_coarsen_p(hipStream_t st, int E, int nf, int nc, const double* Q, const double* in,
+                      double* out);
+void launch_coarsen_h(hipStream_t st, int Nf, int n, const double* Q, const double* in, double* out);
+
+// y[idx[r]] = sum_c G[r, c] x[idx[c]] (FP64 accumulation), r < nd.
+template <typename T>
+void launch_dense(hipStream_t st, int nd, const double* G, const int* idx, const T* x, T* y);
+
+// Vector kernels.
+template <typename T> void launch_fill(hipStream_t st, T* x, T v, size_t n);
+template <typename T> void launch_axpby(hipStream_t st, size_t n, T a, const T* x, T b, T* y);
+template <typename Ta, typename Tb> void launch_cast(hipStream_t st, size_t n, const Ta* a, Tb* b);
+template <typename T>
+void launch_scale_nodes(hipStream_t st, int nn, int NC, const T* s, const T* x, T* y);
+// Chebyshev: r = b - t (t may be null), d = dinv r / theta, x = x0 + d (x0 = 0 if xzero)
+template <typename T>
+void launch_cheb_first(hipStream_t st, size_t n, const T* b, const T* t, const T* dinv, T inv_theta,
+                       T* d, T* x, T* r, bool xzero);
+// Chebyshev: r -= t, d = alpha d + beta dinv r, x += d
+template <typename T>
+void launch_cheb_step(hipStream_t st, size_t n, const T* t, const T* dinv, T alpha, T beta, T* d,
+                      T* x, T* r);
+// y = a x
+template <typename T> void launch_scal(hipStream_t st, size_t n, T a, const T* x, T* y);
+// zero the boundary nodes of an NC-component nodal vector with M nodes per direction
+template <typename T> void launch_mask_boundary(hipStream_t st, int M, int NC, T* x);
+// c = a * b (elementwise)
+template <typename T> void launch_mul(hipStream_t st, size_t n, const T* a, const T* b, T* c);
+// r = b - t
+template <typename T> void launch_sub(hipStream_t st, size_t n, const T* b, const T* t, T* r);
+
+// Reductions into a device FP64 scalar (two stages, deterministic).
+template <typename T>
+void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partial, double* out);
+constexpr int RED_BLOCKS = 1024;
+// Pressure mean of the constant mode: p[e*np] -= mean_e p[e*np].
+template <typename T>
+void launch_remove_mean(hipStream_t st, int E, int np, T* p, double* partial, double* scratch);
+
+// FGMRES helpers (FP64): h[v] = V[v] . w for v < nv (V rows of stride ld),
+// w -= sum_v h[v] V[v], x += sum_v y[v] Z[v].
+void launch_mdot(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* w,
+                 double* partial, double* h);
+void launch_gemv_sub(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* h,
+                     double* w);
+void launch_gemv_add(hipStream_t st, size_t n, int nv, const double* Z, size_t ld, const double* y,
+                     double* x);
+
+}  // namespace wb

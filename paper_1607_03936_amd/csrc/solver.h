@@ -1,0 +1,113 @@
+// Multigrid hierarchies, w-BFBT apply, block preconditioner and FGMRES (host orchestration).
+#pragma once
+
+#include <functional>
+#include <memory>
+#include <vector>
+
+#include "kernels.h"
+
+namespace wb {
+
+// Device allocations owned by one object, freed together.
+class Arena {
+ public:
+  ~Arena();
+  template <typename T>
+  T* alloc(size_t n) {
+    return static_cast<T*>(raw(n * sizeof(T)));
+  }
+  void* raw(size_t bytes);
+  size_t bytes() const { return bytes_; }
+
+ private:
+  std::vector<void*> ptrs_;
+  size_t bytes_ = 0;
+};
+
+// One re-discretized level of a hierarchy (velocity: NC = 3, Dirichlet; Poisson: NC = 1, Neumann).
+template <typename T>
+struct Level {
+  int N = 0, k = 0, NC = 3;
+  bool dir = true;
+  int nn = 0, E = 0;
+  size_t len = 0;          // NC * nn
+  T* coef = nullptr;       // coefficient at Gauss points [E][(k+1)^3]
+  T* dinv = nullptr;       // inverse Jacobi diagonal [len]
+  double lmin = 0, lmax = 0;
+  T *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
+  Rows1D P{}, R{};         // prolongation from / restriction to the next coarser level
+};
+
+template <typename T>
+struct Hierarchy {
+  std::vector<Level<T>> L;
+  int nd = 0;              // coarsest dense (pseudo-)inverse size
+  double* G = nullptr;     // [nd][nd] FP64
+  int* gidx = nullptr;     // dense index -> vector index
+};
+
+// The (k, N) level schedule: halve k to 1, then halve N while N/2 >= 4.
+std::vector<std::pair<int, int>> level_schedule(int N, int k);
+
+struct Solver;
+
+// Preconditioner state in precision T (FP64 or FP32).
+template <typename T>
+struct Precond {
+  Hierarchy<T> A;           // velocity hierarchy (coefficient mu)
+  Hierarchy<T> Pois[2];     // left / right Poisson hierarchies (coefficient 1/w)
+  T* winv[2] = {nullptr, nullptr};  // C^-1, D^-1 per node [nn]
+  T* dk[2] = {nullptr, nullptr};    // inverse diagonal of K_l, K_r [E*np]
+  double klmin[2] = {0, 0}, klmax[2] = {0, 0};
+  // work
+  T *v1 = nullptr, *v2 = nullptr, *vt = nullptr;                       // velocity [3 nn]
+  T *pb = nullptr, *px = nullptr, *pr = nullptr, *pd = nullptr, *pt = nullptr, *pm = nullptr,
+    *py = nullptr;                                                     // pressure [E np]
+  T *cin_u = nullptr, *cin_p = nullptr, *cout_u = nullptr, *cout_p = nullptr;  // casts (FP32)
+};
+
+struct Solver {
+  Mesh m;
+  wb_opts o;
+  hipStream_t st = nullptr;
+  Arena arena;
+  double* mu_q = nullptr;   // fine viscosity (FP64)
+  std::unique_ptr<Precond<double>> pd;
+  std::unique_ptr<Precond<float>> pf;
+  double* red_partial = nullptr;  // reduction scratch
+  double* red_out = nullptr;      // [8] device scalars
+  // Krylov space
+  size_t n_tot = 0;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *hbuf = nullptr, *mpartial = nullptr;
+  double *bvec = nullptr, *xvec = nullptr;
+  double t_setup = 0.0;
+  // learned correction (optional)
+  struct Learned* learned = nullptr;
+  int learned_used = 0, fell_back = 0;
+  ~Solver();
+};
+
+Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes, const wb_opts& o,
+                      hipStream_t st);
+
+template <typename T>
+void apply_wbfbt(Solver& s, Precond<T>& P, const T* r, T* z);
+template <typename T>
+void apply_vcycle_A(Solver& s, Precond<T>& P, const T* r, T* z);
+template <typename T>
+void apply_K(Solver& s, Precond<T>& P, int side, const T* p, T* y);
+template <typename T>
+void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* r, T* z);
+template <typename T>
+void apply_precond(Solver& s, Precond<T>& P, const T* ru, const T* rp, T* zu, T* zp);
+
+// Preconditioner in the solver's configured precision, FP64 in and out.
+void apply_precond_any(Solver& s, const double* ru, const double* rp, double* zu, double* zp);
+
+wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep);
+
+// host helpers
+double dot_host(Solver& s, size_t n, const double* x, const double* y);
+
+}  // namespace wb

@@ -1,0 +1,792 @@
+// Hierarchy setup, V-cycles, w-BFBT apply (eq. 7, 11), block preconditioner (eq. 3) and
+// flexible GMRES.  Host code orchestrating the kernels of kernels.hip on one stream.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "solver.h"
+
+namespace wb {
+
+// ------------------------------------------------------------------ arena
+Arena::~Arena() {
+  for (void* p : ptrs_) (void)hipFree(p);
+}
+void* Arena::raw(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess)
+    throw Error{WB_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  ptrs_.push_back(p);
+  bytes_ += bytes;
+  return p;
+}
+
+std::vector<std::pair<int, int>> level_schedule(int N, int k) {
+  std::vector<std::pair<int, int>> out{{N, k}};
+  while (k > 1) {
+    k = std::max(1, k / 2);
+    out.push_back({N, k});
+  }
+  while (N % 2 == 0 && N / 2 >= 4) {
+    N /= 2;
+    out.push_back({N, k});
+  }
+  return out;
+}
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------- host linear algebra
+// In-place inverse of an SPD matrix via Cholesky (n small).
+void spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> Lm(A);
+  for (int j = 0; j < n; ++j) {
+    double s = Lm[j * n + j];
+    for (int p = 0; p < j; ++p) s -= Lm[j * n + p] * Lm[j * n + p];
+    if (!(s > 0.0)) throw Error{WB_ENAN, "coarse operator is not positive definite"};
+    const double d = std::sqrt(s);
+    Lm[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = Lm[i * n + j];
+      for (int p = 0; p < j; ++p) t -= Lm[i * n + p] * Lm[j * n + p];
+      Lm[i * n + j] = t / d;
+    }
+  }
+  // solve for each unit vector
+  std::vector<double> col(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int p = 0; p < i; ++p) t -= Lm[i * n + p] * col[p];
+      col[i] = t / Lm[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = col[i];
+      for (int p = i + 1; p < n; ++p) t -= Lm[p * n + i] * col[p];
+      col[i] = t / Lm[i * n + i];
+    }
+    for (int i = 0; i < n; ++i) A[i * n + c] = col[i];
+  }
+}
+
+// Largest eigenvalue of a symmetric tridiagonal matrix (cyclic Jacobi on the dense form).
+double tridiag_max_eig(const std::vector<double>& dg, const std::vector<double>& off) {
+  const int m = (int)dg.size();
+  std::vector<double> A(m * m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    A[i * m + i] = dg[i];
+    if (i + 1 < m) A[i * m + i + 1] = A[(i + 1) * m + i] = off[i];
+  }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double offn = 0.0;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) offn += A[p * m + q] * A[p * m + q];
+    if (offn < 1e-30) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A[p * m + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < m; ++r) {
+          const double arp = A[r * m + p], arq = A[r * m + q];
+          A[r * m + p] = c * arp - s * arq;
+          A[r * m + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < m; ++r) {
+          const double apr = A[p * m + r], aqr = A[q * m + r];
+          A[p * m + r] = c * apr - s * aqr;
+          A[q * m + r] = s * apr + c * aqr;
+        }
+      }
+  }
+  double mx = -1e300;
+  for (int i = 0; i < m; ++i) mx = std::max(mx, A[i * m + i]);
+  return mx;
+}
+
+// Counter-based splitmix64 uniform in [-1, 1): u_i = 2 U(mix(seed * 2^32 + i)) - 1.
+void splitmix_vector(unsigned long long seed, size_t n, std::vector<double>& out) {
+  out.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    unsigned long long z = (seed << 32) + (unsigned long long)i + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z = z ^ (z >> 31);
+    out[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+}
+
+// ---------------------------------------------------------------- 1D transfer tables
+Rows1D upload_rows(Arena& ar, const std::vector<std::vector<std::pair<int, double>>>& rows, int ncols) {
+  int W = 1;
+  for (auto& r : rows) W = std::max<int>(W, (int)r.size());
+  const int R = (int)rows.size();
+  std::vector<int> cnt(R), col((size_t)R * W, 0);
+  std::vector<double> val((size_t)R * W, 0.0);
+  for (int i = 0; i < R; ++i) {
+    cnt[i] = (int)rows[i].size();
+    for (int t = 0; t < cnt[i]; ++t) {
+      col[(size_t)i * W + t] = rows[i][t].first;
+      val[(size_t)i * W + t] = rows[i][t].second;
+    }
+  }
+  Rows1D o;
+  o.rows = R;
+  o.cols = ncols;
+  o.W = W;
+  o.cnt = ar.alloc<int>(R);
+  o.col = ar.alloc<int>((size_t)R * W);
+  o.val = ar.alloc<double>((size_t)R * W);
+  WB_HIP(hipMemcpy(o.cnt, cnt.data(), sizeof(int) * R, hipMemcpyHostToDevice));
+  WB_HIP(hipMemcpy(o.col, col.data(), sizeof(int) * R * W, hipMemcpyHostToDevice));
+  WB_HIP(hipMemcpy(o.val, val.data(), sizeof(double) * R * W, hipMemcpyHostToDevice));
+  return o;
+}
+
+// P1[i_f][I_c]: coarse continuous 1D basis (Nc elements, order kc) at the fine nodes (Nf, kf).
+void make_transfer(Arena& ar, int Nc, int kc, int Nf, int kf, Rows1D& P, Rows1D& R) {
+  const Tables& tf = tables(kf);
+  const Tables& tc = tables(kc);
+  const int Mf = kf * Nf + 1, Mc = kc * Nc + 1;
+  std::vector<std::vector<std::pair<int, double>>> prow(Mf), rrow(Mc);
+  for (int i = 0; i < Mf; ++i) {
+    const int ef = std::min(i / kf, Nf - 1), a = i - ef * kf;
+    const double x = (ef + 0.5 * (tf.xl[a] + 1.0)) / Nf;
+    const int ec = std::min((int)std::floor(x * Nc + 1e-12), Nc - 1);
+    const double xi = 2.0 * (x * Nc - ec) - 1.0;
+    double V[NMAX];
+    lagrange(kc + 1, tc.xl, 1, &xi, V, nullptr);
+    for (int b = 0; b <= kc; ++b)
+      if (std::fabs(V[b]) > 1e-14) prow[i].push_back({ec * kc + b, V[b]});
+  }
+  for (int i = 0; i < Mf; ++i)
+    for (auto& cv : prow[i]) rrow[cv.first].push_back({i, cv.second});
+  P = upload_rows(ar, prow, Mc);
+  R = upload_rows(ar, rrow, Mf);
+}
+
+// Coarsening matrix Q[qc][(s, qf)] of the L2 adjoint of element-wise interpolation.
+std::vector<double> coarsen_matrix(int nf, int nc, int children) {
+  const Tables& tf = tables(nf - 1);
+  const Tables& tc = tables(nc - 1);
+  const int W = children * nf;
+  std::vector<double> Q((size_t)nc * W);
+  for (int s = 0; s < children; ++s)
+    for (int qf = 0; qf < nf; ++qf) {
+      const double xi = children == 1 ? tf.xg[qf] : 0.5 * (tf.xg[qf] + 2 * s - 1);
+      double V[NMAX];
+      lagrange(nc, tc.xg, 1, &xi, V, nullptr);
+      for (int qc = 0; qc < nc; ++qc)
+        Q[(size_t)qc * W + s * nf + qf] = V[qc] * (tf.wg[qf] / children) / tc.wg[qc];
+    }
+  return Q;
+}
+
+// Reference divergence matrix without the (h/2)^2 factor: bhat[m][c][i] = -sum_q psi_m d_c phi_i w.
+std::vector<double> make_bhat(int k) {
+  const Tables& t = tables(k);
+  const int n = k + 1, n3 = n * n * n;
+  std::vector<double> bh((size_t)t.np * 3 * n3, 0.0);
+  for (int m = 0; m < t.np; ++m)
+    for (int li = 0; li < n3; ++li) {
+      const int a = li % n, b = (li / n) % n, c = li / (n * n);
+      double s[3] = {0, 0, 0};
+      for (int qz = 0; qz < n; ++qz)
+        for (int qy = 0; qy < n; ++qy)
+          for (int qx = 0; qx < n; ++qx) {
+            const double w = t.wg[qx] * t.wg[qy] * t.wg[qz];
+            const double psi = t.L[t.ma[m] * n + qx] * t.L[t.mb[m] * n + qy] * t.L[t.mc[m] * n + qz];
+            s[0] += w * psi * t.D1[qx * n + a] * t.B[qy * n + b] * t.B[qz * n + c];
+            s[1] += w * psi * t.B[qx * n + a] * t.D1[qy * n + b] * t.B[qz * n + c];
+            s[2] += w * psi * t.B[qx * n + a] * t.B[qy * n + b] * t.D1[qz * n + c];
+          }
+      for (int c3 = 0; c3 < 3; ++c3) bh[((size_t)m * 3 + c3) * n3 + li] = -s[c3];
+    }
+  return bh;
+}
+
+template <typename T>
+void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out) {
+  launch_fill<T>(st, out, T(0), L.len);
+  launch_op<T>(st, L.dir ? (F_A | F_DIR) : F_A, L.NC, L.N, L.k, in, out, L.coef, nullptr, nullptr,
+               nullptr, nullptr);
+}
+
+// Chebyshev-accelerated Jacobi (degree steps) for A x = b, A given as a callback.
+template <typename T, typename Op>
+void chebyshev(hipStream_t st, const Op& op, size_t len, const T* dinv, double lmin, double lmax,
+               int degree, const T* b, T* x, bool xzero, T* r, T* d, T* t) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (xzero) {
+    launch_cheb_first<T>(st, len, b, nullptr, dinv, (T)(1.0 / theta), d, x, r, true);
+  } else {
+    op(x, t);
+    launch_cheb_first<T>(st, len, b, t, dinv, (T)(1.0 / theta), d, x, r, false);
+  }
+  for (int s = 1; s < degree; ++s) {
+    op(d, t);
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    launch_cheb_step<T>(st, len, t, dinv, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), d, x, r);
+    rho = rho_new;
+  }
+}
+
+template <typename Op>
+double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, const std::vector<double>& b0,
+                   int steps, double* r, double* z, double* p, double* q) {
+  hipStream_t st = s.st;
+  WB_HIP(hipMemcpyAsync(r, b0.data(), sizeof(double) * len, hipMemcpyHostToDevice, st));
+  launch_mul<double>(st, len, dinv, r, z);
+  WB_HIP(hipMemcpyAsync(p, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
+  double rz = dot_host(s, len, r, z);
+  std::vector<double> alphas, betas;
+  for (int it = 0; it < steps; ++it) {
+    op(p, q);
+    const double pq = dot_host(s, len, p, q);
+    if (!(rz > 0.0) || !(pq > 0.0)) break;
+    const double alpha = rz / pq;
+    launch_axpby<double>(st, len, -alpha, q, 1.0, r);
+    launch_mul<double>(st, len, dinv, r, z);
+    const double rz_new = dot_host(s, len, r, z);
+    const double beta = rz_new / rz;
+    alphas.push_back(alpha);
+    betas.push_back(beta);
+    rz = rz_new;
+    launch_axpby<double>(st, len, 1.0, z, beta, p);
+    if (!(rz > 0.0)) break;
+  }
+  const int m = (int)alphas.size();
+  WB_REQUIRE(m > 0, WB_ENAN, "eigenvalue estimate failed (zero operator?)");
+  std::vector<double> dg(m), off(std::max(0, m - 1));
+  for (int j = 0; j < m; ++j) {
+    dg[j] = 1.0 / alphas[j] + (j > 0 ? betas[j - 1] / alphas[j - 1] : 0.0);
+    if (j + 1 < m) off[j] = std::sqrt(betas[j]) / alphas[j];
+  }
+  return tridiag_max_eig(dg, off);
+}
+
+// Build an FP64 hierarchy on `coef0` (velocity if NC == 3, Poisson if NC == 1).
+void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef0, int seed_base) {
+  hipStream_t st = s.st;
+  Arena& ar = s.arena;
+  auto sched = level_schedule(s.m.N, s.m.k);
+  const int nl = (int)sched.size();
+  H.L.resize(nl);
+  for (int li = 0; li < nl; ++li) {
+    Level<double>& L = H.L[li];
+    L.N = sched[li].first;
+    L.k = sched[li].second;
+    L.NC = NC;
+    L.dir = NC == 3;
+    const int M = L.k * L.N + 1, n = L.k + 1;
+    L.nn = M * M * M;
+    L.E = L.N * L.N * L.N;
+    L.len = (size_t)NC * L.nn;
+    const size_t ncoef = (size_t)L.E * n * n * n;
+    L.coef = ar.alloc<double>(ncoef);
+    if (li == 0) {
+      WB_HIP(hipMemcpyAsync(L.coef, coef0, sizeof(double) * ncoef, hipMemcpyDeviceToDevice, st));
+    } else {
+      const Level<double>& F = H.L[li - 1];
+      if (F.N == L.N) {
+        auto Q = coarsen_matrix(F.k + 1, n, 1);
+        double* dQ = ar.alloc<double>(Q.size());
+        WB_HIP(hipMemcpy(dQ, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
+        launch_coarsen_p(st, L.E, F.k + 1, n, dQ, F.coef, L.coef);
+      } else {
+        auto Q = coarsen_matrix(n, n, 2);
+        double* dQ = ar.alloc<double>(Q.size());
+        WB_HIP(hipMemcpy(dQ, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
+        launch_coarsen_h(st, F.N, n, dQ, F.coef, L.coef);
+      }
+    }
+    L.dinv = ar.alloc<double>(L.len);
+    launch_fill<double>(st, L.dinv, 0.0, L.len);
+    launch_diag(st, NC, L.N, L.k, L.dir, L.coef, L.dinv);
+    launch_invert_diag(st, NC, L.N, L.k, L.dir, L.dinv);
+    L.x = ar.alloc<double>(L.len);
+    L.b = ar.alloc<double>(L.len);
+    L.r = ar.alloc<double>(L.len);
+    L.d = ar.alloc<double>(L.len);
+    L.t = ar.alloc<double>(L.len);
+    for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
+    if (li > 0) make_transfer(ar, L.N, L.k, H.L[li - 1].N, H.L[li - 1].k, H.L[li - 1].P, H.L[li - 1].R);
+  }
+  // Chebyshev bounds from the Lanczos estimate on every smoothed level
+  for (int li = 0; li + 1 < nl; ++li) {
+    Level<double>& L = H.L[li];
+    std::vector<double> b0;
+    splitmix_vector((unsigned long long)(seed_base + li), L.len, b0);
+    const int M = L.k * L.N + 1;
+    if (L.dir) {
+      for (size_t i = 0; i < L.len; ++i) {
+        const size_t g = i % L.nn;
+        const int gi = (int)(g % M), gj = (int)((g / M) % M), gl = (int)(g / ((size_t)M * M));
+        if (gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1 || gl == 0 || gl == M - 1) b0[i] = 0.0;
+      }
+    } else {
+      double mean = 0.0;
+      for (double v : b0) mean += v;
+      mean /= (double)b0.size();
+      for (double& v : b0) v -= mean;
+    }
+    auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out); };
+    const double lam = lanczos_max(s, op, L.len, L.dinv, b0, s.o.lanczos_steps, L.x, L.b, L.r, L.d);
+    L.lmin = 0.1 * lam;
+    L.lmax = 1.1 * lam;
+    for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
+  }
+  // coarsest: dense inverse (velocity: interior DOFs, SPD) or pseudo-inverse (Poisson, Neumann)
+  Level<double>& C = H.L[nl - 1];
+  const int M = C.k * C.N + 1;
+  std::vector<int> idx;
+  for (size_t i = 0; i < C.len; ++i) {
+    const size_t g = i % C.nn;
+    const int gi = (int)(g % M), gj = (int)((g / M) % M), gl = (int)(g / ((size_t)M * M));
+    const bool bnd = gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1 || gl == 0 || gl == M - 1;
+    if (!C.dir || !bnd) idx.push_back((int)i);
+  }
+  const int nd = (int)idx.size();
+  std::vector<double> Ad((size_t)nd * nd), col(C.len);
+  for (int j = 0; j < nd; ++j) {
+    launch_fill<double>(st, C.x, 0.0, C.len);
+    const double one = 1.0;
+    WB_HIP(hipMemcpyAsync(C.x + idx[j], &one, sizeof(double), hipMemcpyHostToDevice, st));
+    level_op<double>(st, C, C.x, C.t);
+    WB_HIP(hipMemcpyAsync(col.data(), C.t, sizeof(double) * C.len, hipMemcpyDeviceToHost, st));
+    WB_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nd; ++i) Ad[(size_t)i * nd + j] = col[idx[i]];
+  }
+  for (int i = 0; i < nd; ++i)
+    for (int j = i + 1; j < nd; ++j) {
+      const double a = 0.5 * (Ad[(size_t)i * nd + j] + Ad[(size_t)j * nd + i]);
+      Ad[(size_t)i * nd + j] = Ad[(size_t)j * nd + i] = a;
+    }
+  if (C.dir) {
+    spd_inverse(Ad, nd);
+  } else {
+    double c = 0.0;
+    for (int i = 0; i < nd; ++i) c += Ad[(size_t)i * nd + i];
+    c /= nd;
+    for (auto& v : Ad) v += c;
+    spd_inverse(Ad, nd);
+    // G = Pi (L + c 1 1^T)^-1 Pi, Pi = I - 1 1^T / nd
+    std::vector<double> rm(nd, 0.0), cm(nd, 0.0);
+    double tm = 0.0;
+    for (int i = 0; i < nd; ++i)
+      for (int j = 0; j < nd; ++j) {
+        rm[i] += Ad[(size_t)i * nd + j] / nd;
+        cm[j] += Ad[(size_t)i * nd + j] / nd;
+        tm += Ad[(size_t)i * nd + j] / ((double)nd * nd);
+      }
+    for (int i = 0; i < nd; ++i)
+      for (int j = 0; j < nd; ++j) Ad[(size_t)i * nd + j] += -rm[i] - cm[j] + tm;
+  }
+  H.nd = nd;
+  H.G = ar.alloc<double>((size_t)nd * nd);
+  H.gidx = ar.alloc<int>(nd);
+  WB_HIP(hipMemcpy(H.G, Ad.data(), sizeof(double) * Ad.size(), hipMemcpyHostToDevice));
+  WB_HIP(hipMemcpy(H.gidx, idx.data(), sizeof(int) * nd, hipMemcpyHostToDevice));
+  launch_fill<double>(st, C.x, 0.0, C.len);
+  launch_fill<double>(st, C.t, 0.0, C.len);
+}
+
+// FP32 copy of an FP64 hierarchy (coefficients and diagonals cast; transfers and the FP64
+// coarsest inverse shared).
+void cast_hierarchy(Solver& s, const Hierarchy<double>& Hd, Hierarchy<float>& Hf) {
+  hipStream_t st = s.st;
+  Arena& ar = s.arena;
+  Hf.L.resize(Hd.L.size());
+  for (size_t li = 0; li < Hd.L.size(); ++li) {
+    const Level<double>& D = Hd.L[li];
+    Level<float>& L = Hf.L[li];
+    L.N = D.N;
+    L.k = D.k;
+    L.NC = D.NC;
+    L.dir = D.dir;
+    L.nn = D.nn;
+    L.E = D.E;
+    L.len = D.len;
+    L.lmin = D.lmin;
+    L.lmax = D.lmax;
+    L.P = D.P;
+    L.R = D.R;
+    const size_t ncoef = (size_t)D.E * (D.k + 1) * (D.k + 1) * (D.k + 1);
+    L.coef = ar.alloc<float>(ncoef);
+    launch_cast<double, float>(st, ncoef, D.coef, L.coef);
+    L.dinv = ar.alloc<float>(L.len);
+    launch_cast<double, float>(st, L.len, D.dinv, L.dinv);
+    L.x = ar.alloc<float>(L.len);
+    L.b = ar.alloc<float>(L.len);
+    L.r = ar.alloc<float>(L.len);
+    L.d = ar.alloc<float>(L.len);
+    L.t = ar.alloc<float>(L.len);
+    for (float* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<float>(st, v, 0.0f, L.len);
+  }
+  Hf.nd = Hd.nd;
+  Hf.G = Hd.G;
+  Hf.gidx = Hd.gidx;
+}
+
+template <typename T>
+void alloc_work(Solver& s, Precond<T>& P) {
+  Arena& ar = s.arena;
+  const size_t vl = (size_t)3 * s.m.nn, pl = (size_t)s.m.E * s.m.np;
+  for (T** v : {&P.v1, &P.v2, &P.vt}) *v = ar.alloc<T>(vl);
+  for (T** v : {&P.pb, &P.px, &P.pr, &P.pd, &P.pt, &P.pm, &P.py}) *v = ar.alloc<T>(pl);
+  P.cin_u = ar.alloc<T>(vl);
+  P.cout_u = ar.alloc<T>(vl);
+  P.cin_p = ar.alloc<T>(pl);
+  P.cout_p = ar.alloc<T>(pl);
+}
+
+}  // namespace
+
+double dot_host(Solver& s, size_t n, const double* x, const double* y) {
+  launch_dot<double>(s.st, n, x, y, s.red_partial, s.red_out);
+  double v = 0.0;
+  WB_HIP(hipMemcpyAsync(&v, s.red_out, sizeof(double), hipMemcpyDeviceToHost, s.st));
+  WB_HIP(hipStreamSynchronize(s.st));
+  return v;
+}
+
+// ------------------------------------------------------------------ applies
+template <typename T>
+void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
+  hipStream_t st = s.st;
+  Level<T>& L = H.L[li];
+  if (li + 1 == (int)H.L.size()) {
+    if (L.dir) launch_fill<T>(st, x, T(0), L.len);
+    launch_dense<T>(st, H.nd, H.G, H.gidx, b, x);
+    return;
+  }
+  auto op = [&](const T* in, T* out) { level_op<T>(st, L, in, out); };
+  const int deg = s.o.cheb_degree;
+  chebyshev<T>(st, op, L.len, L.dinv, L.lmin, L.lmax, deg, b, x, true, L.r, L.d, L.t);
+  op(x, L.t);
+  launch_sub<T>(st, L.len, b, L.t, L.r);
+  Level<T>& C = H.L[li + 1];
+  launch_kron<T>(st, L.R, L.NC, C.dir, false, L.r, C.b);
+  vcycle<T>(s, H, li + 1, C.b, C.x);
+  launch_kron<T>(st, L.P, L.NC, L.dir, true, C.x, x);
+  chebyshev<T>(st, op, L.len, L.dinv, L.lmin, L.lmax, deg, b, x, false, L.r, L.d, L.t);
+}
+
+template <typename T>
+const T* fine_mu(Solver& s, Precond<T>& P) {
+  return P.A.L[0].coef;
+}
+
+template <typename T>
+void apply_K(Solver& s, Precond<T>& P, int side, const T* p, T* y) {
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  launch_fill<T>(st, P.vt, T(0), (size_t)3 * m.nn);
+  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr, nullptr, nullptr);
+  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y, P.winv[side],
+               nullptr);
+}
+
+template <typename T>
+void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* b, T* x) {
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  const size_t pl = (size_t)m.E * m.np;
+  auto op = [&](const T* in, T* out) { apply_K<T>(s, P, side, in, out); };
+  const int deg = s.o.cheb_degree;
+  chebyshev<T>(st, op, pl, P.dk[side], P.klmin[side], P.klmax[side], deg, b, x, true, P.pr, P.pd,
+               P.pt);
+  op(x, P.pt);
+  launch_sub<T>(st, pl, b, P.pt, P.pr);
+  Hierarchy<T>& H = P.Pois[side];
+  Level<T>& L0 = H.L[0];
+  launch_fill<T>(st, L0.b, T(0), L0.len);
+  launch_modal_IT<T>(st, m.N, m.k, P.pr, L0.b);
+  vcycle<T>(s, H, 0, L0.b, L0.x);
+  launch_modal_I<T>(st, m.N, m.k, L0.x, x, true);
+  chebyshev<T>(st, op, pl, P.dk[side], P.klmin[side], P.klmax[side], deg, b, x, false, P.pr, P.pd,
+               P.pt);
+  launch_remove_mean<T>(st, m.E, m.np, x, s.red_partial, s.red_out + 1);
+}
+
+template <typename T>
+void apply_wbfbt(Solver& s, Precond<T>& P, const T* r, T* z) {
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  const size_t pl = (size_t)m.E * m.np, vl = (size_t)3 * m.nn;
+  WB_HIP(hipMemcpyAsync(P.pb, r, sizeof(T) * pl, hipMemcpyDeviceToDevice, st));
+  launch_remove_mean<T>(st, m.E, m.np, P.pb, s.red_partial, s.red_out + 2);
+  apply_vcycle_K<T>(s, P, 1, P.pb, P.py);
+  // middle product B C^-1 A D^-1 B^T
+  launch_fill<T>(st, P.v1, T(0), vl);
+  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, P.py, nullptr, nullptr, nullptr);
+  launch_fill<T>(st, P.v2, T(0), vl);
+  launch_op<T>(st, F_A | F_DIR, 3, m.N, m.k, P.v1, P.v2, fine_mu(s, P), nullptr, nullptr, P.winv[1],
+               nullptr);
+  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, P.winv[0], nullptr);
+  launch_remove_mean<T>(st, m.E, m.np, P.pm, s.red_partial, s.red_out + 2);
+  apply_vcycle_K<T>(s, P, 0, P.pm, z);
+}
+
+template <typename T>
+void apply_vcycle_A(Solver& s, Precond<T>& P, const T* r, T* z) {
+  vcycle<T>(s, P.A, 0, r, z);
+}
+
+template <typename T>
+void apply_precond(Solver& s, Precond<T>& P, const T* ru, const T* rp, T* zu, T* zp) {
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  const size_t vl = (size_t)3 * m.nn;
+  apply_wbfbt<T>(s, P, rp, zp);
+  launch_fill<T>(st, P.v1, T(0), vl);
+  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, zp, nullptr, nullptr, nullptr);
+  launch_sub<T>(st, vl, ru, P.v1, P.v2);
+  apply_vcycle_A<T>(s, P, P.v2, zu);
+}
+
+template void apply_wbfbt<double>(Solver&, Precond<double>&, const double*, double*);
+template void apply_wbfbt<float>(Solver&, Precond<float>&, const float*, float*);
+template void apply_vcycle_A<double>(Solver&, Precond<double>&, const double*, double*);
+template void apply_vcycle_A<float>(Solver&, Precond<float>&, const float*, float*);
+template void apply_K<double>(Solver&, Precond<double>&, int, const double*, double*);
+template void apply_K<float>(Solver&, Precond<float>&, int, const float*, float*);
+template void apply_vcycle_K<double>(Solver&, Precond<double>&, int, const double*, double*);
+template void apply_vcycle_K<float>(Solver&, Precond<float>&, int, const float*, float*);
+template void apply_precond<double>(Solver&, Precond<double>&, const double*, const double*, double*,
+                                    double*);
+template void apply_precond<float>(Solver&, Precond<float>&, const float*, const float*, float*,
+                                   float*);
+
+void apply_precond_any(Solver& s, const double* ru, const double* rp, double* zu, double* zp) {
+  if (s.o.precond_prec == WB_FP64) {
+    apply_precond<double>(s, *s.pd, ru, rp, zu, zp);
+    return;
+  }
+  Precond<float>& P = *s.pf;
+  const size_t vl = (size_t)3 * s.m.nn, pl = (size_t)s.m.E * s.m.np;
+  launch_cast<double, float>(s.st, vl, ru, P.cin_u);
+  launch_cast<double, float>(s.st, pl, rp, P.cin_p);
+  apply_precond<float>(s, P, P.cin_u, P.cin_p, P.cout_u, P.cout_p);
+  launch_cast<float, double>(s.st, vl, P.cout_u, zu);
+  launch_cast<float, double>(s.st, pl, P.cout_p, zp);
+}
+
+// ------------------------------------------------------------------ setup
+Solver::~Solver() {}
+
+Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes, const wb_opts& o,
+                      hipStream_t st) {
+  WB_REQUIRE(m.k >= 2 && m.k <= 4, WB_EUNSUPPORTED, "Stokes solves need 2 <= k <= 4");
+  WB_REQUIRE(o.cheb_degree >= 1 && o.restart >= 1 && o.max_iter >= 1 && o.rtol > 0, WB_EINVAL,
+             "bad solver options");
+  WB_REQUIRE(o.a_l >= 1.0 && o.a_r >= 1.0, WB_EINVAL, "boundary amplification must be >= 1");
+  WB_REQUIRE(o.precond_prec == WB_FP64 || o.precond_prec == WB_FP32, WB_EUNSUPPORTED,
+             "preconditioner precision not built");
+  const double t0 = now_s();
+  std::unique_ptr<Solver> sp(new Solver());
+  Solver& s = *sp;
+  s.m = m;
+  s.o = o;
+  s.st = st;
+  Arena& ar = s.arena;
+  s.red_partial = ar.alloc<double>(RED_BLOCKS * 128);
+  s.red_out = ar.alloc<double>(8);
+  const int n3 = (m.k + 1) * (m.k + 1) * (m.k + 1);
+  s.mu_q = ar.alloc<double>((size_t)m.E * n3);
+  WB_HIP(hipMemcpyAsync(s.mu_q, mu_q, sizeof(double) * m.E * n3, hipMemcpyDeviceToDevice, st));
+
+  s.pd.reset(new Precond<double>());
+  Precond<double>& P = *s.pd;
+  build_hierarchy(s, P.A, 3, s.mu_q, 1000);
+  // weights C = M(a_l sqrt(mu)), D = M(a_r sqrt(mu)) (eq. 7, 11); stored inverted
+  const double amps[2] = {o.a_l, o.a_r};
+  auto bh = make_bhat(m.k);
+  double* dbh = ar.alloc<double>(bh.size());
+  WB_HIP(hipMemcpy(dbh, bh.data(), sizeof(double) * bh.size(), hipMemcpyHostToDevice));
+  alloc_work(s, P);
+  for (int side = 0; side < 2; ++side) {
+    P.winv[side] = ar.alloc<double>(m.nn);
+    launch_fill<double>(st, P.winv[side], 0.0, m.nn);
+    launch_lumped_mass(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
+    launch_invert_diag(st, 1, m.N, m.k, false, P.winv[side]);
+    P.dk[side] = ar.alloc<double>((size_t)m.E * m.np);
+    launch_diag_K(st, m.N, m.k, dbh, P.winv[side], P.dk[side]);
+    // Poisson hierarchy on the coefficient 1/w at the Gauss points (eq. 9-10)
+    double* cq = ar.alloc<double>((size_t)m.E * n3);
+    launch_poisson_coef(st, m.N, m.k, amps[side], s.mu_q, cq);
+    build_hierarchy(s, P.Pois[side], 1, cq, side == 0 ? 2000 : 3000);
+  }
+  // Chebyshev bounds on the discontinuous K_w levels
+  for (int side = 0; side < 2; ++side) {
+    std::vector<double> b0;
+    const size_t pl = (size_t)m.E * m.np;
+    splitmix_vector(side == 0 ? 4000ULL : 5000ULL, pl, b0);
+    double mean = 0.0;
+    for (int e = 0; e < m.E; ++e) mean += b0[(size_t)e * m.np];
+    mean /= m.E;
+    for (int e = 0; e < m.E; ++e) b0[(size_t)e * m.np] -= mean;
+    auto op = [&](const double* in, double* out) { apply_K<double>(s, P, side, in, out); };
+    const double lam =
+        lanczos_max(s, op, pl, P.dk[side], b0, o.lanczos_steps, P.pr, P.pd, P.pt, P.pm);
+    P.klmin[side] = 0.1 * lam;
+    P.klmax[side] = 1.1 * lam;
+  }
+  if (o.precond_prec == WB_FP32) {
+    s.pf.reset(new Precond<float>());
+    Precond<float>& F = *s.pf;
+    cast_hierarchy(s, P.A, F.A);
+    for (int side = 0; side < 2; ++side) {
+      cast_hierarchy(s, P.Pois[side], F.Pois[side]);
+      F.winv[side] = ar.alloc<float>(m.nn);
+      launch_cast<double, float>(st, m.nn, P.winv[side], F.winv[side]);
+      F.dk[side] = ar.alloc<float>((size_t)m.E * m.np);
+      launch_cast<double, float>(st, (size_t)m.E * m.np, P.dk[side], F.dk[side]);
+      F.klmin[side] = P.klmin[side];
+      F.klmax[side] = P.klmax[side];
+    }
+    alloc_work(s, F);
+  }
+  // Krylov space
+  s.n_tot = (size_t)3 * m.nn + (size_t)m.E * m.np;
+  const int R = o.restart;
+  s.V = ar.alloc<double>((size_t)(R + 1) * s.n_tot);
+  s.Z = ar.alloc<double>((size_t)R * s.n_tot);
+  s.w = ar.alloc<double>(s.n_tot);
+  s.bvec = ar.alloc<double>(s.n_tot);
+  s.xvec = ar.alloc<double>(s.n_tot);
+  s.hbuf = ar.alloc<double>((size_t)3 * (R + 2));
+  s.mpartial = ar.alloc<double>((size_t)256 * (R + 2));
+  WB_HIP(hipStreamSynchronize(st));
+  s.t_setup = now_s() - t0;
+  return sp.release();
+}
+
+// ------------------------------------------------------------------ FGMRES
+namespace {
+void stokes_matvec(Solver& s, const double* x, double* y) {
+  const Mesh& m = s.m;
+  const size_t vl = (size_t)3 * m.nn;
+  launch_fill<double>(s.st, y, 0.0, vl);
+  launch_op<double>(s.st, F_A | F_BT | F_B | F_DIR, 3, m.N, m.k, x, y, s.mu_q, x + vl, y + vl, nullptr,
+                    nullptr);
+}
+}  // namespace
+
+wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep) {
+  const double t0 = now_s();
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  const size_t n = s.n_tot, vl = (size_t)3 * m.nn, pl = (size_t)m.E * m.np;
+  const int R = s.o.restart;
+  s.learned_used = s.fell_back = 0;
+  // b = [f with zero boundary entries; 0]
+  WB_HIP(hipMemcpyAsync(s.bvec, f, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
+  launch_mask_boundary<double>(st, m.M, 3, s.bvec);
+  launch_fill<double>(st, s.bvec + vl, 0.0, pl);
+  launch_fill<double>(st, s.xvec, 0.0, n);
+  const double bnorm = std::sqrt(dot_host(s, n, s.bvec, s.bvec));
+  int it = 0;
+  double relres = 0.0;
+  wb_status status = WB_OK;
+  if (bnorm == 0.0) {
+    relres = 0.0;
+  } else {
+    WB_HIP(hipMemcpyAsync(s.w, s.bvec, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    double beta = bnorm;
+    std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), hh(2 * (R + 2) + 1);
+    bool done = false;
+    while (!done) {
+      std::fill(H.begin(), H.end(), 0.0);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      launch_scal<double>(st, n, 1.0 / beta, s.w, s.V);
+      int jdone = 0;
+      for (int j = 0; j < R; ++j) {
+        double* vj = s.V + (size_t)j * n;
+        double* zj = s.Z + (size_t)j * n;
+        apply_precond_any(s, vj, vj + vl, zj, zj + vl);
+        stokes_matvec(s, zj, s.w);
+        // classical Gram-Schmidt, two passes
+        double* h1 = s.hbuf;
+        double* h2 = s.hbuf + (R + 2);
+        launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, h1);
+        launch_gemv_sub(st, n, j + 1, s.V, n, h1, s.w);
+        launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, h2);
+        launch_gemv_sub(st, n, j + 1, s.V, n, h2, s.w);
+        launch_dot<double>(st, n, s.w, s.w, s.red_partial, s.hbuf + 2 * (R + 2));
+        WB_HIP(hipMemcpyAsync(hh.data(), s.hbuf, sizeof(double) * (2 * (R + 2) + 1),
+                              hipMemcpyDeviceToHost, st));
+        WB_HIP(hipStreamSynchronize(st));
+        const double nrm = std::sqrt(hh[2 * (R + 2)]);
+        if (!std::isfinite(nrm)) throw Error{WB_ENAN, "NaN/Inf in the Krylov vector"};
+        for (int i = 0; i <= j; ++i) H[(size_t)i * R + j] = hh[i] + hh[(R + 2) + i];
+        H[(size_t)(j + 1) * R + j] = nrm;
+        if (nrm > 0.0) launch_scal<double>(st, n, 1.0 / nrm, s.w, s.V + (size_t)(j + 1) * n);
+        for (int i = 0; i < j; ++i) {
+          const double a = H[(size_t)i * R + j], b = H[(size_t)(i + 1) * R + j];
+          H[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
+          H[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = H[(size_t)j * R + j], b = H[(size_t)(j + 1) * R + j];
+        const double den = std::hypot(a, b);
+        cs[j] = a / den;
+        sn[j] = b / den;
+        H[(size_t)j * R + j] = den;
+        H[(size_t)(j + 1) * R + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++it;
+        jdone = j + 1;
+        if (s.o.verbose) fprintf(stderr, "fgmres %4d  %.3e\n", it, std::fabs(g[j + 1]) / bnorm);
+        if (std::fabs(g[j + 1]) <= s.o.rtol * bnorm || it >= s.o.max_iter || nrm == 0.0) break;
+      }
+      // y = H^-1 g, x += Z y
+      std::vector<double> y(jdone);
+      for (int i = jdone - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int c = i + 1; c < jdone; ++c) t -= H[(size_t)i * R + c] * y[c];
+        y[i] = t / H[(size_t)i * R + i];
+      }
+      WB_HIP(hipMemcpyAsync(s.hbuf, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, st));
+      launch_gemv_add(st, n, jdone, s.Z, n, s.hbuf, s.xvec);
+      // true residual
+      stokes_matvec(s, s.xvec, s.w);
+      launch_axpby<double>(st, n, 1.0, s.bvec, -1.0, s.w);
+      beta = std::sqrt(dot_host(s, n, s.w, s.w));
+      relres = beta / bnorm;
+      if (relres <= s.o.rtol) done = true;
+      else if (it >= s.o.max_iter) {
+        status = WB_ENOCONV;
+        done = true;
+      }
+    }
+  }
+  launch_remove_mean<double>(st, m.E, m.np, s.xvec + vl, s.red_partial, s.red_out + 3);
+  WB_HIP(hipMemcpyAsync(u, s.xvec, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
+  WB_HIP(hipMemcpyAsync(p, s.xvec + vl, sizeof(double) * pl, hipMemcpyDeviceToDevice, st));
+  WB_HIP(hipStreamSynchronize(st));
+  if (rep) {
+    rep->iters = it;
+    rep->rel_res = relres;
+    rep->t_setup_s = s.t_setup;
+    rep->t_solve_s = now_s() - t0;
+    rep->fell_back = s.fell_back;
+    rep->learned_used = s.learned_used;
+    rep->device_bytes = s.arena.bytes();
+  }
+  return status;
+}
+
+}  // namespace wb

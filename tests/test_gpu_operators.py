@@ -1,0 +1,157 @@
+"""GPU parity of the operator layer against the FP64 oracle (through the C-ABI).
+
+Sizes span several thread blocks with a ragged tail: the operator kernel packs
+256 / (k+1)^2 elements per block (64, 28, 16, 10 for k = 1..4).
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, sinker, solver
+from synthetic import WORKLOADS, sinker_centers, random_vector
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _wb():
+    from paper_1607_03936_amd import wbfbt
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    wbfbt.lib()
+    return wbfbt
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+CASES = [(9, 1), (8, 2), (7, 3), (5, 4)]
+
+
+@pytest.mark.parametrize("N,k", CASES)
+def test_sinker_viscosity_and_load(N, k):
+    wb = _wb()
+    c = sinker_centers(11, 6)
+    m = wb.Mesh(N, k)
+    v = wb.Viscosity.sinker(m, c, 200.0, 0.1, 1e-3, 1e3)
+    mq, mn = v.get()
+    om = fem.Mesh(N, k)
+    want_q = sinker.viscosity(om.quad_points(), c, 200.0, 0.1, 1e-3, 1e3).reshape(-1)
+    want_n = sinker.viscosity(om.node_xyz, c, 200.0, 0.1, 1e-3, 1e3)
+    assert _rel(host(mq), want_q) < 1e-13
+    assert _rel(host(mn), want_n) < 1e-13
+    f = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, c, 200.0, 0.1, 10.0, f)
+    F = fem.assemble_load(om, sinker.body_force(om.quad_points(), c, 200.0, 0.1, 10.0))
+    F[om.vel_boundary] = 0.0
+    assert _rel(host(f), F) < 1e-13
+
+
+@pytest.mark.parametrize("N,k", CASES)
+def test_apply_A_matches_assembled(N, k):
+    wb = _wb()
+    om = fem.Mesh(N, k)
+    rng = np.random.default_rng(N * 10 + k)
+    mu_q = np.exp(rng.uniform(-6, 6, (om.E, om.n ** 3)))        # contrast ~1e5
+    mu_n = np.exp(rng.uniform(-6, 6, om.n_nodes))
+    m = wb.Mesh(N, k)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(mu_n))
+    u = random_vector(3, om.u_dof)
+    y = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    wb.wb_apply_A(m, v, dev(u), y)
+    A = fem.assemble_A(om, mu_q)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0.0                                   # boundary input is ignored
+    want = A @ ui
+    want[om.vel_boundary] = 0.0                                 # boundary output is zero
+    got = host(y)
+    assert _rel(got, want) < 1e-12
+    assert np.all(got[om.vel_boundary] == 0.0)
+
+
+@pytest.mark.parametrize("N,k", CASES[1:])
+def test_apply_B_BT_stokes_match_assembled(N, k):
+    wb = _wb()
+    om = fem.Mesh(N, k)
+    rng = np.random.default_rng(k)
+    mu_q = np.exp(rng.uniform(-3, 3, (om.E, om.n ** 3)))
+    m = wb.Mesh(N, k)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(np.ones(om.n_nodes)))
+    u = random_vector(5, om.u_dof)
+    p = random_vector(6, om.p_dof)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0.0
+    B = fem.assemble_B(om)
+    pg = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    wb.wb_apply_B(m, dev(u), pg)
+    assert _rel(host(pg), B @ ui) < 1e-12
+    ug = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    wb.wb_apply_BT(m, dev(p), ug)
+    want = B.T @ p
+    want[om.vel_boundary] = 0.0
+    assert _rel(host(ug), want) < 1e-12
+    yu = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    yp = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    wb.wb_apply_stokes(m, v, dev(u), dev(p), yu, yp)
+    A = fem.assemble_A(om, mu_q)
+    wu = A @ ui + B.T @ p
+    wu[om.vel_boundary] = 0.0
+    assert _rel(host(yu), wu) < 1e-12
+    assert _rel(host(yp), B @ ui) < 1e-12
+
+
+def test_apply_A_fp32_error_is_single_precision():
+    wb = _wb()
+    N, k = 8, 2
+    om = fem.Mesh(N, k)
+    rng = np.random.default_rng(0)
+    mu_q = np.exp(rng.uniform(-3, 3, (om.E, om.n ** 3)))
+    m = wb.Mesh(N, k)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(np.ones(om.n_nodes)))
+    u = random_vector(1, om.u_dof)
+    y32 = torch.empty(m.u_len, dtype=torch.float32, device="cuda")
+    wb.wb_apply_A_lowp(m, v, wb.WB_FP32, dev(u).float(), y32)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0
+    want = fem.assemble_A(om, mu_q) @ ui
+    want[om.vel_boundary] = 0
+    err = np.linalg.norm(host(y32).astype(np.float64) - want) / np.linalg.norm(want)
+    assert 1e-9 < err < 1e-5
+
+
+@pytest.mark.parametrize("name", ["c2", "c5"])
+def test_apply_A_full_size_sampled_rows(name):
+    # the workload sizes, checked on sampled rows computed element by element by the oracle
+    wb = _wb()
+    w = WORKLOADS[name]
+    c = w.centers()
+    m = wb.Mesh(w.N, w.k)
+    v = wb.Viscosity.sinker(m, c, w.delta, w.omega, w.mu_min, w.mu_max)
+    om = fem.Mesh(w.N, w.k)
+    u = random_vector(17, om.u_dof)
+    u[om.vel_boundary] = 0.0
+    y = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    wb.wb_apply_A(m, v, dev(u), y)
+    got = host(y)
+
+    def mu_of(els):
+        return sinker.viscosity(om.quad_points(els), c, w.delta, w.omega, w.mu_min, w.mu_max)
+
+    rng = np.random.default_rng(99)
+    interior = om.vel_interior
+    dofs = rng.choice(interior, 200, replace=False)
+    # include the first and last interior DOFs (block tails) and DOFs next to the boundary
+    dofs = np.concatenate([dofs, interior[:3], interior[-3:]])
+    want = fem.apply_A_rows(om, mu_of, u, dofs)
+    scale = np.abs(want).max()
+    assert np.abs(got[dofs] - want).max() <= 1e-12 * scale
+    assert np.all(got[om.vel_boundary] == 0.0)
