@@ -9,7 +9,7 @@
  *   -div[mu (grad u + grad u^T)] + grad p = f,   -div u = 0,   u = 0 on the
  *   boundary of the unit cube (eq. 1), discretized with continuous nodal Q_k
  *   velocity and discontinuous modal P_{k-1} pressure on a uniform N^3
- *   hexahedral mesh (Sec. 1.1, eq. 2).
+ *   hexahedral mesh (Sec. 1.2, eq. 2).
  *
  * Conventions shared by every entry point
  * ----------------------------------------
@@ -63,7 +63,7 @@ typedef struct wb_solver wb_solver;
  * Chebyshev-accelerated point-Jacobi smoothing with 3 pre- and 3 post-steps,
  * GMRES restarted every 100 iterations, relative residual 1e-6 (Sec. 6-7). */
 typedef struct {
-  double a_l, a_r;        /* Dirichlet boundary amplification of w_l, w_r (eq. 11) */
+  double a_l, a_r;        /* Dirichlet boundary amplification of w_l, w_r (Sec. 5) */
   int cheb_degree;        /* Chebyshev-Jacobi steps per smoothing (3)              */
   int lanczos_steps;      /* CG steps for the largest-eigenvalue estimate (10)     */
   int restart;            /* FGMRES restart length (100)                           */
@@ -88,7 +88,7 @@ typedef struct {
 WB_API void wb_opts_default(wb_opts* o);
 WB_API const char* wb_last_error(void);
 
-/* ---- mesh (Sec. 1.1): uniform N^3 hexahedra of the unit cube, order k ---- */
+/* ---- mesh (Sec. 1.2): uniform N^3 hexahedra of the unit cube, order k ---- */
 /* N >= 1, 1 <= k <= 4.  Creates structured metadata only (no device memory). */
 WB_API wb_status wb_mesh_create(int N, int k, wb_mesh** out);
 WB_API void wb_mesh_destroy(wb_mesh* m);
@@ -118,13 +118,16 @@ WB_API wb_status wb_rhs_sinker(const wb_mesh* m, const double* centers_host, int
                                double delta, double omega, double beta, double* f_dev, void* stream);
 
 /* ---- discrete operators of eq. (2), matrix-free ----
- * A: viscous stress, (A u)_i = sum_e int_e 2 mu eps(u) : eps(phi_i)   (Sec. 1.1, 3.1)
+ * A: viscous stress, (A u)_i = sum_e int_e 2 mu eps(u) : eps(phi_i)   (Sec. 1.2, 3.1)
  * B: divergence, (B u)_{e,m} = -int_e psi_m div u  (B = -div, Sec. 3.1)
  * B^T: gradient, (B^T p)_i = -sum_e int_e p div phi_i
  * u, y: [3][n_nodes]; p: [E][n_p].  Outputs are overwritten.  In-place (u == y) is not allowed. */
 WB_API wb_status wb_apply_A(const wb_mesh* m, const wb_visc* v, const double* u, double* y, void* stream);
 WB_API wb_status wb_apply_B(const wb_mesh* m, const double* u, double* p, void* stream);
 WB_API wb_status wb_apply_BT(const wb_mesh* m, const double* p, double* u, void* stream);
+/* y += A u (no zeroing of y first): accumulate the viscous-stress apply into y. */
+WB_API wb_status wb_apply_A_add(const wb_mesh* m, const wb_visc* v, const double* u, double* y,
+                                void* stream);
 /* Fused Stokes operator of eq. (2): yu = A u + B^T p, yp = B u (one kernel). */
 WB_API wb_status wb_apply_stokes(const wb_mesh* m, const wb_visc* v, const double* u, const double* p,
                                  double* yu, double* yp, void* stream);
@@ -133,7 +136,7 @@ WB_API wb_status wb_apply_stokes(const wb_mesh* m, const wb_visc* v, const doubl
 WB_API wb_status wb_apply_A_lowp(const wb_mesh* m, const wb_visc* v, int prec, const float* u,
                                  float* y, void* stream);
 
-/* ---- solver: w-BFBT (eq. 7, 11) + p/h-multigrid (Sec. 6) + FGMRES (eq. 3) ----
+/* ---- solver: w-BFBT (eq. 8, Sec. 5) + p/h-multigrid (Sec. 6) + FGMRES (eq. 3) ----
  * Builds the velocity multigrid hierarchy, the weights C = M(w_l), D = M(w_r),
  * w = a sqrt(mu), the two pressure-Poisson hierarchies and the Krylov space.
  * opts may be NULL (defaults).  Synchronizes `stream`. */
@@ -142,14 +145,14 @@ WB_API wb_status wb_solver_create(const wb_mesh* m, const wb_visc* v, const wb_o
 WB_API void wb_solver_destroy(wb_solver* s);
 
 /* z = S_w^-1 r: K_l^-1 (B C^-1 A D^-1 B^T) K_r^-1 r with each K^-1 one
- * V-cycle (eq. 7); r, z: [E][n_p] FP64; the output has zero mean. */
+ * V-cycle (eq. 8); r, z: [E][n_p] FP64; the output has zero mean. */
 WB_API wb_status wb_apply_wbfbt(wb_solver* s, const double* r, double* z, void* stream);
 /* z = (one V-cycle of A) r, Sec. 6; r, z: [3][n_nodes]. */
 WB_API wb_status wb_apply_vcycle_A(wb_solver* s, const double* r, double* z, void* stream);
-/* K_w = B D_w^-1 B^T with w the left (side 0) or right (side 1) weight (eq. 7). */
+/* K_w = B D_w^-1 B^T with w the left (side 0) or right (side 1) weight (eq. 8). */
 WB_API wb_status wb_apply_K(wb_solver* s, int side, const double* p, double* y, void* stream);
 /* z = (one K_w V-cycle) r: discontinuous smoothing, Q_k Poisson V-cycle with
- * coefficient 1/w (eq. 9-10, Sec. 6), smoothing, mean removal. */
+ * coefficient 1/w (eq. 11-12, Sec. 6), smoothing, mean removal. */
 WB_API wb_status wb_apply_vcycle_K(wb_solver* s, int side, const double* r, double* z, void* stream);
 /* Upper block-triangular preconditioner of eq. (3):
  * z_p = S_w^-1 r_p, z_u = (A V-cycle)(r_u - B^T z_p). */
@@ -186,6 +189,15 @@ WB_API wb_status wb_learned_train(wb_solver* s, const double* centers_host, cons
 /* Flat FP32 parameter blob: query size with params == NULL. HOST pointers. */
 WB_API wb_status wb_learned_get(wb_solver* s, float* params, long long* n_params);
 WB_API wb_status wb_learned_set(wb_solver* s, const float* params, long long n_params);
+
+/* ---- instrumentation ----
+ * When enabled, every operator-kernel launch is bracketed by HIP events on the
+ * stream it is launched on.  wb_profile_summary writes lines
+ * "<kernel class>\t<launches>\t<total ms>" into buf (NUL-terminated, truncated
+ * to len) after waiting for the recorded events, optionally clearing them;
+ * returns the full summary length. */
+WB_API void wb_profile_enable(int on);
+WB_API long long wb_profile_summary(char* buf, long long len, int reset);
 
 #ifdef __cplusplus
 }

@@ -8,10 +8,10 @@ Everything here is written from the paper's definitions, in numpy/scipy,
 assembled and slow on purpose:
 
 * ``fem``      -- reference element, mesh numbering, assembled A, B, B^T, F,
-                  lumped weighted velocity masses (eq. 4, 7, 11), transfers.
+                  lumped weighted velocity masses (eq. 4, 8, Sec. 5), transfers.
 * ``sinker``   -- the multi-sinker viscosity and body force (Sec. 2.1).
 * ``solver``   -- Chebyshev-Jacobi smoothing, Lanczos eigenvalue estimate,
-                  multigrid V-cycles, the w-BFBT apply (eq. 7), the block
+                  multigrid V-cycles, the w-BFBT apply (eq. 8), the block
                   preconditioner (eq. 3), flexible GMRES and direct solves.
 * ``learned``  -- the small convolutional coarse-correction network.
 

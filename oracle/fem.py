@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-Follows the paper's discretization (Sec. 1.1, eq. 2): continuous nodal Q_k
+Follows the paper's discretization (Sec. 1.2, eq. 2): continuous nodal Q_k
 velocity on a uniform hexahedral mesh of the unit cube, discontinuous modal
 P_{k-1} pressure, no-slip Dirichlet velocity.  Readings where the paper is
 silent: velocity nodes at the Gauss-Lobatto-Legendre (GLL) points; Gauss-Legendre
@@ -141,7 +141,7 @@ class Mesh:
         # velocity DOF masks ([3][n_nodes] layout)
         self.vel_boundary = np.tile(self.boundary, 3)
         self.vel_interior = np.flatnonzero(~self.vel_boundary)
-        # elements whose closure touches the boundary (eq. 11's Omega_D)
+        # elements whose closure touches the boundary (the set Omega_D of Sec. 5)
         self.touches_boundary = np.any((self.eidx == 0) | (self.eidx == N - 1), axis=1)
 
     @property
@@ -264,7 +264,7 @@ def assemble_load(mesh: Mesh, f_q: np.ndarray) -> np.ndarray:
 
 
 def element_amplification(mesh: Mesh, a: float) -> np.ndarray:
-    """a_e = a on elements touching the Dirichlet boundary, 1 elsewhere (eq. 11)."""
+    """a_e = a on elements touching the Dirichlet boundary, 1 elsewhere (Sec. 5)."""
     return np.where(mesh.touches_boundary, a, 1.0)
 
 
@@ -272,7 +272,7 @@ def lumped_weighted_mass(mesh: Mesh, w_nodes: np.ndarray, a_e: np.ndarray) -> np
     """Row sums of the weighted velocity mass matrix built with GLL quadrature.
 
     M_e[i, j] = sum_{q in GLL} a_e w(x_q) phi_i(x_q) phi_j(x_q) omega_q |J|;
-    the lumped diagonal is M 1 (eq. 4 applied to the velocity space, eq. 7).
+    the lumped diagonal is M 1 (eq. 4 applied to the velocity space, eq. 8).
     w_nodes: weight function at the global velocity nodes, [n_nodes].
     Returns the diagonal per node (identical for the 3 components)."""
     n = mesh.n

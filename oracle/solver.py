@@ -5,10 +5,10 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 Written from the paper's definitions:
 
 * upper block-triangular right preconditioner and GMRES (eq. 3);
-* BFBT / w-BFBT inverse Schur approximation (eq. 6, 7) with lumped
-  sqrt(mu)-weighted velocity masses and Dirichlet amplification (eq. 11);
+* BFBT / w-BFBT inverse Schur approximation (eq. 7, 8) with lumped
+  sqrt(mu)-weighted velocity masses and Dirichlet amplification (Sec. 5);
 * pressure Poisson K_w = B D_w^-1 B^T and its V-cycle through a continuous Q_k
-  Poisson re-discretization with coefficient 1/w (eq. 9, 10, Sec. 6);
+  Poisson re-discretization with coefficient 1/w (eq. 11, 12, Sec. 6);
 * p- then h-multigrid V-cycles with Chebyshev-accelerated point-Jacobi
   smoothing, 3 pre and 3 post, re-discretized coarse operators with the
   viscosity coarsened by the L2 adjoint of element-wise interpolation (Sec. 6).
@@ -272,7 +272,7 @@ class Stokes:
         return self.B @ (self.Cinv * (self.A @ (self.Dinv * (self.B.T @ q))))
 
     def wbfbt_exact(self, r):
-        """S_w^-1 r = K_l^+ (B C^-1 A D^-1 B^T) K_r^+ r (eq. 7) with exact inverses."""
+        """S_w^-1 r = K_l^+ (B C^-1 A D^-1 B^T) K_r^+ r (eq. 8) with exact inverses."""
         y = self.k_pinv_solve(self.Kr, r)
         return self.remove_mean(self.k_pinv_solve(self.Kl, self.middle(y)))
 
@@ -299,7 +299,7 @@ class Preconditioner:
     def __init__(self, st: Stokes, degree=3):
         self.st = st
         m = st.mesh
-        # velocity hierarchy on mu (Sec. 6), Poisson hierarchies on 1/w (eq. 9-11)
+        # velocity hierarchy on mu (Sec. 6), Poisson hierarchies on 1/w (eq. 11, 12, Sec. 5)
         self.A_mg = Hierarchy(m.N, m.k, st.mu_q, "velocity", 1000, degree)
         sqmu = np.sqrt(st.mu_q)
         c_l = 1.0 / (fem.element_amplification(m, st.a_l)[:, None] * sqmu)

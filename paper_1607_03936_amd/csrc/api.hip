@@ -1,5 +1,6 @@
 // C-ABI entry points (declared in include/wbfbt.h).  Every call converts internal
 // exceptions into a wb_status and a thread-local message.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -426,6 +427,30 @@ wb_status wb_solver_levels(wb_solver* sh, int which, int* nlevels, int* Ns, int*
       if (ks) ks[i] = H.L[i].k;
       if (lmax) lmax[i] = H.L[i].lmax;
     }
+    return WB_OK;
+  });
+}
+
+void wb_profile_enable(int on) { profile_enable(on != 0); }
+
+long long wb_profile_summary(char* buf, long long len, int reset) {
+  std::string s = profile_summary(reset != 0);
+  if (buf && len > 0) {
+    const size_t n = std::min<size_t>((size_t)len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return (long long)s.size();
+}
+
+wb_status wb_apply_A_add(const wb_mesh* mh, const wb_visc* v, const double* u, double* y, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && v && u && y, WB_EINVAL, "NULL argument");
+    WB_REQUIRE(u != y, WB_EINVAL, "in-place apply is not allowed");
+    const Mesh& m = mh->m;
+    launch_op<double>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q, nullptr, nullptr, nullptr,
+                      nullptr);
+    check_launch();
     return WB_OK;
   });
 }

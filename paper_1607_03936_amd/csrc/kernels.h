@@ -1,9 +1,16 @@
 // Launchers of the HIP kernels (host side).  All launches go to `st`.
 #pragma once
 
+#include <string>
+
 #include "wb_internal.h"
 
 namespace wb {
+
+// HIP-event timing of operator launches (off by default); summary lines are
+// "<kernel class>\t<launches>\t<total ms>".
+void profile_enable(bool on);
+std::string profile_summary(bool reset);
 
 // Operator flags: viscous/Poisson stiffness, gradient B^T p, divergence B u, Dirichlet mask.
 enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8 };
@@ -22,7 +29,7 @@ void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* c
 // dinv = 1/diag, 1 on Dirichlet nodes (if dir).
 void launch_invert_diag(hipStream_t st, int NC, int N, int k, bool dir, double* d);
 
-// Lumped sqrt(mu)-weighted GLL mass with amplification `amp` on boundary elements (eq. 7, 11):
+// Lumped sqrt(mu)-weighted GLL mass with amplification `amp` on boundary elements (eq. 8, Sec. 5):
 // accumulated into cnodes (zeroed), [nn].
 void launch_lumped_mass(hipStream_t st, int N, int k, double amp, const double* mu_nodes,
                         double* cnodes);
@@ -41,7 +48,7 @@ void launch_sinker_nodes(hipStream_t st, int N, int k, const double* x1, const d
 // F_z += int f_z phi_i  (F zeroed by the caller), boundary entries untouched (0).
 void launch_load(hipStream_t st, int N, int k, const double* f_q, double* F);
 // Coefficient transforms at the Gauss points: c = scale / (amp_e sqrt(mu)) with amp_e on
-// boundary elements (Poisson coefficient 1/w of eq. 9-11) or a plain FP64->FP32 cast.
+// boundary elements (Poisson coefficient 1/w of eq. 11-12 and Sec. 5) or a plain FP64->FP32 cast.
 void launch_poisson_coef(hipStream_t st, int N, int k, double amp, const double* mu_q, double* c_q);
 
 // Transfers: tensor product of a 1D sparse matrix (rows: cnt / col / val, width W).

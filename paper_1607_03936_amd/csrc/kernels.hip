@@ -4,15 +4,76 @@
 // values are interpolated to the (k+1)^3 Gauss points by three 1D contractions,
 // differentiated there with the collocation derivative of the Gauss-Lagrange
 // basis, multiplied by the pointwise coefficient and pulled back by the
-// transposed contractions (Sec. 1.1 discretization of eq. 2).  Thread layout:
+// transposed contractions (Sec. 1.2 discretization, eq. 2).  Thread layout:
 // n^2 threads per element, each holding a z-column in registers; x and y
 // contractions exchange through LDS.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "kernels.h"
 
 namespace wb {
+
+// ------------------------------------------------------------------ profiling
+// Optional HIP-event timing of operator launches, keyed by kernel class.
+namespace prof {
+struct Rec {
+  std::string key;
+  hipEvent_t a, b;
+};
+static std::mutex mu;
+static bool on = false;
+static std::vector<Rec> recs;
+static std::vector<hipEvent_t> pool;
+
+static hipEvent_t get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace prof
+
+void profile_enable(bool on) {
+  std::lock_guard<std::mutex> g(prof::mu);
+  prof::on = on;
+}
+
+std::string profile_summary(bool reset) {
+  std::lock_guard<std::mutex> g(prof::mu);
+  std::map<std::string, std::pair<long, double>> agg;
+  for (auto& r : prof::recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& x = agg[r.key];
+      x.first += 1;
+      x.second += ms;
+    }
+  }
+  std::string out;
+  for (auto& kv : agg) {
+    char line[256];
+    snprintf(line, sizeof(line), "%s\t%ld\t%.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    out += line;
+  }
+  if (reset) {
+    for (auto& r : prof::recs) {
+      prof::pool.push_back(r.a);
+      prof::pool.push_back(r.b);
+    }
+    prof::recs.clear();
+  }
+  return out;
+}
 
 namespace {
 
@@ -340,8 +401,24 @@ void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, co
   const int M = k * N + 1, E = N * N * N, nn = M * M * M;
   const T hh = (T)(0.5 / N);
   const KT<n, T> tb = make_kt<n, T>(k);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (prof::on) {
+    std::lock_guard<std::mutex> g(prof::mu);
+    ea = prof::get_event();
+    eb = prof::get_event();
+    if (ea) (void)hipEventRecord(ea, st);
+  }
   hipLaunchKernelGGL((k_op<n, NC, T, F>), dim3(grid_for(E, EPB)), dim3(EPB * NN), 0, st, tb, N, k,
                      M, E, nn, hh, u, y, coef, pin, pout, sin, sout);
+  if (ea && eb) {
+    std::lock_guard<std::mutex> g(prof::mu);
+    (void)hipEventRecord(eb, st);
+    char key[160];
+    snprintf(key, sizeof(key), "op nc=%d k=%d N=%d flags=%s%s%s%s%s %s", NC, k, N,
+             (F & F_A) ? "A" : "", (F & F_BT) ? "+BT" : "", (F & F_B) ? "+B" : "",
+             (F & F_DIR) ? "+dir" : "", sin ? "+scale" : "", sizeof(T) == 8 ? "f64" : "f32");
+    prof::recs.push_back({key, ea, eb});
+  }
 }
 
 template <int n, typename T>

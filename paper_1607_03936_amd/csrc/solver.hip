@@ -1,4 +1,4 @@
-// Hierarchy setup, V-cycles, w-BFBT apply (eq. 7, 11), block preconditioner (eq. 3) and
+// Hierarchy setup, V-cycles, w-BFBT apply (eq. 8, Sec. 5), block preconditioner (eq. 3) and
 // flexible GMRES.  Host code orchestrating the kernels of kernels.hip on one stream.
 #include <algorithm>
 #include <chrono>
@@ -610,7 +610,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.pd.reset(new Precond<double>());
   Precond<double>& P = *s.pd;
   build_hierarchy(s, P.A, 3, s.mu_q, 1000);
-  // weights C = M(a_l sqrt(mu)), D = M(a_r sqrt(mu)) (eq. 7, 11); stored inverted
+  // weights C = M(a_l sqrt(mu)), D = M(a_r sqrt(mu)) (eq. 8, Sec. 5); stored inverted
   const double amps[2] = {o.a_l, o.a_r};
   auto bh = make_bhat(m.k);
   double* dbh = ar.alloc<double>(bh.size());
@@ -623,7 +623,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     launch_invert_diag(st, 1, m.N, m.k, false, P.winv[side]);
     P.dk[side] = ar.alloc<double>((size_t)m.E * m.np);
     launch_diag_K(st, m.N, m.k, dbh, P.winv[side], P.dk[side]);
-    // Poisson hierarchy on the coefficient 1/w at the Gauss points (eq. 9-10)
+    // Poisson hierarchy on the coefficient 1/w at the Gauss points (eq. 11, 12)
     double* cq = ar.alloc<double>((size_t)m.E * n3);
     launch_poisson_coef(st, m.N, m.k, amps[side], s.mu_q, cq);
     build_hierarchy(s, P.Pois[side], 1, cq, side == 0 ? 2000 : 3000);

@@ -1,6 +1,6 @@
 // Host-side 1D quadrature rules and polynomial tables for the Q_k x P_{k-1}
 // discretization: Gauss-Legendre quadrature, Gauss-Lobatto-Legendre nodes,
-// Lagrange and Legendre bases (Sec. 1.1 discretization; node set and
+// Lagrange and Legendre bases (Sec. 1.2 discretization; node set and
 // quadrature rule as documented in the header of wbfbt.h).
 #include <cmath>
 #include <cstring>

@@ -58,6 +58,7 @@ SIGNATURES = {
     "wb_apply_A": (I, [VP, VP, VP, VP, VP]),
     "wb_apply_B": (I, [VP, VP, VP, VP]),
     "wb_apply_BT": (I, [VP, VP, VP, VP]),
+    "wb_apply_A_add": (I, [VP, VP, VP, VP, VP]),
     "wb_apply_stokes": (I, [VP, VP, VP, VP, VP, VP, VP]),
     "wb_apply_A_lowp": (I, [VP, VP, I, VP, VP, VP]),
     "wb_solver_create": (I, [VP, VP, ctypes.POINTER(wb_opts), VP, PVP]),
@@ -74,6 +75,8 @@ SIGNATURES = {
     "wb_learned_train": (I, [VP, VP, VP, I, I, I, D, ctypes.POINTER(D), VP]),
     "wb_learned_get": (I, [VP, VP, ctypes.POINTER(LL)]),
     "wb_learned_set": (I, [VP, VP, LL]),
+    "wb_profile_enable": (None, [I]),
+    "wb_profile_summary": (LL, [ctypes.c_char_p, LL, I]),
 }
 
 
@@ -191,6 +194,28 @@ def wb_apply_A(mesh, visc, u, y, stream=None):
     import torch
     _check(lib().wb_apply_A(mesh.h, visc.h, _ptr(u, torch.float64, mesh.u_len),
                             _ptr(y, torch.float64, mesh.u_len), _stream(stream)))
+
+
+def wb_apply_A_add(mesh, visc, u, y, stream=None):
+    import torch
+    _check(lib().wb_apply_A_add(mesh.h, visc.h, _ptr(u, torch.float64, mesh.u_len),
+                                _ptr(y, torch.float64, mesh.u_len), _stream(stream)))
+
+
+def wb_profile_enable(on: bool):
+    lib().wb_profile_enable(1 if on else 0)
+
+
+def wb_profile_summary(reset: bool = True):
+    """{kernel class: (launches, total ms)} of the event-timed operator launches."""
+    n = lib().wb_profile_summary(None, 0, 0)
+    buf = ctypes.create_string_buffer(int(n) + 1)
+    lib().wb_profile_summary(buf, n + 1, 1 if reset else 0)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        key, cnt, ms = line.split("\t")
+        out[key] = (int(cnt), float(ms))
+    return out
 
 
 def wb_apply_A_lowp(mesh, visc, prec, u, y, stream=None):

@@ -26,8 +26,8 @@ class Workload:
     delta: float
     omega: float
     dr: float         # dynamic ratio mu_max / mu_min
-    a_l: float        # left boundary amplification (eq. 11)
-    a_r: float        # right boundary amplification (eq. 11)
+    a_l: float        # left boundary amplification (Sec. 5)
+    a_r: float        # right boundary amplification (Sec. 5)
     seed: int
     beta: float = 10.0
 

@@ -61,7 +61,7 @@ def _pair(name):
 def test_setup_products(name):
     w, st, P, m, v, s = _pair(name)
     om = st.mesh
-    # weights (eq. 7, 11)
+    # weights (eq. 8, Sec. 5)
     assert _rel(host(s.query(0, 0, om.n_nodes)), 1.0 / st.C_nodes) < 1e-13
     assert _rel(host(s.query(1, 0, om.n_nodes)), 1.0 / st.D_nodes) < 1e-13
     # discontinuous K diagonals

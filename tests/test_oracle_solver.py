@@ -87,7 +87,7 @@ def test_wbfbt_invariances():
     st = _small(3, 2, a_l=1.0, a_r=2.0)
     r = st.remove_mean(np.random.default_rng(5).uniform(-1, 1, st.np_))
     z = st.wbfbt_exact(r)
-    # scaling C and D by constants leaves S_w^-1 unchanged (Sec. 3 remark after the lower bound)
+    # scaling C and D by constants leaves S_w^-1 unchanged (Sec. 3, remark after the lower-bound corollary)
     Cinv, Dinv = st.Cinv.copy(), st.Dinv.copy()
     st.Cinv, st.Dinv = Cinv / 3.0, Dinv * 7.0
     st.Kl = (st.B @ sp.diags(st.Cinv) @ st.B.T).tocsr()
