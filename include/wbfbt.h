@@ -72,6 +72,8 @@ typedef struct {
   int precond_prec;       /* wb_prec of the preconditioner: WB_FP64, WB_FP32 or
                              WB_BF16 (FP32 with BF16 MFMA contractions)            */
   int use_learned;        /* 1: learned coarse correction in the velocity V-cycle  */
+  int p_schedule;         /* order coarsening: 0 halves k (4->2->1, 3->1, 2->1),
+                             1 lowers it by one (4->3->2->1, 3->2->1)              */
   int verbose;            /* 1: print the residual history to stderr              */
 } wb_opts;
 
@@ -163,6 +165,13 @@ WB_API wb_status wb_apply_precond(wb_solver* s, const double* r_u, const double*
  * Returns WB_ENOCONV if max_iter is reached (u, p hold the last iterate). */
 WB_API wb_status wb_solve(wb_solver* s, const double* f, double* u, double* p, wb_report* rep,
                           void* stream);
+
+/* Sub-solves of the paper's Table 3: GMRES (same restart / rtol / max_iter as wb_solve, x0 = 0)
+ * on one block preconditioned by one of its V-cycles: which = 0 solves A u = b (b, x
+ * [3][n_nodes], boundary entries 0), which = 1 / 2 solves K_l p = b / K_r p = b (b, x [E][n_p];
+ * the mean of b is removed first and x has zero mean).  Iterations and residual go to rep. */
+WB_API wb_status wb_subsolve(wb_solver* s, int which, const double* b, double* x, wb_report* rep,
+                             void* stream);
 
 /* Inspection of setup products (for tests).  what:
  *   0 C^-1 per node [n_nodes]          1 D^-1 per node [n_nodes]

@@ -55,6 +55,16 @@ Mesh make_mesh(int N, int k) {
   return m;
 }
 
+// Face-array workspace of the scatter operators for standalone applies on this mesh
+// (allocated on first use; calls sharing a mesh handle must be stream-ordered).
+void* mesh_work(const wb_mesh* mh) {
+  if (!mh->work) {
+    const size_t bytes = op_workspace_bytes(3, mh->m.N, mh->m.k, sizeof(double));
+    WB_HIP(hipMalloc(&mh->work, bytes));
+  }
+  return mh->work;
+}
+
 std::vector<double> node_coords_1d(const Mesh& m) {
   const Tables& t = tables(m.k);
   std::vector<double> x1(m.M);
@@ -98,7 +108,11 @@ wb_status wb_mesh_create(int N, int k, wb_mesh** out) {
   });
 }
 
-void wb_mesh_destroy(wb_mesh* m) { delete m; }
+void wb_mesh_destroy(wb_mesh* m) {
+  if (!m) return;
+  if (m->work) (void)hipFree(m->work);
+  delete m;
+}
 
 wb_status wb_mesh_sizes(const wb_mesh* m, long long* n_nodes, long long* n_elem, int* n_p) {
   return guard([&] {
@@ -213,9 +227,8 @@ wb_status wb_apply_A(const wb_mesh* mh, const wb_visc* v, const double* u, doubl
     WB_REQUIRE(mh && v && u && y, WB_EINVAL, "NULL argument");
     WB_REQUIRE(u != y, WB_EINVAL, "in-place apply is not allowed");
     const Mesh& m = mh->m;
-    launch_fill<double>(S(stream), y, 0.0, (size_t)3 * m.nn);
     launch_op<double>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q, nullptr, nullptr, nullptr,
-                      nullptr);
+                      false, mesh_work(mh));
     check_launch();
     return WB_OK;
   });
@@ -227,7 +240,7 @@ wb_status wb_apply_B(const wb_mesh* mh, const double* u, double* p, void* stream
     const Mesh& m = mh->m;
     WB_REQUIRE(m.k >= 2, WB_EUNSUPPORTED, "B needs k >= 2");
     launch_op<double>(S(stream), F_B | F_DIR, 3, m.N, m.k, u, nullptr, nullptr, nullptr, p, nullptr,
-                      nullptr);
+                      false, nullptr);
     check_launch();
     return WB_OK;
   });
@@ -238,9 +251,8 @@ wb_status wb_apply_BT(const wb_mesh* mh, const double* p, double* u, void* strea
     WB_REQUIRE(mh && u && p, WB_EINVAL, "NULL argument");
     const Mesh& m = mh->m;
     WB_REQUIRE(m.k >= 2, WB_EUNSUPPORTED, "B^T needs k >= 2");
-    launch_fill<double>(S(stream), u, 0.0, (size_t)3 * m.nn);
     launch_op<double>(S(stream), F_BT | F_DIR, 3, m.N, m.k, nullptr, u, nullptr, p, nullptr, nullptr,
-                      nullptr);
+                      false, mesh_work(mh));
     check_launch();
     return WB_OK;
   });
@@ -253,9 +265,8 @@ wb_status wb_apply_stokes(const wb_mesh* mh, const wb_visc* v, const double* u, 
     WB_REQUIRE(u != yu, WB_EINVAL, "in-place apply is not allowed");
     const Mesh& m = mh->m;
     WB_REQUIRE(m.k >= 2, WB_EUNSUPPORTED, "Stokes operator needs k >= 2");
-    launch_fill<double>(S(stream), yu, 0.0, (size_t)3 * m.nn);
     launch_op<double>(S(stream), F_A | F_BT | F_B | F_DIR, 3, m.N, m.k, u, yu, v->mu_q, p, yp, nullptr,
-                      nullptr);
+                      false, mesh_work(mh));
     check_launch();
     return WB_OK;
   });
@@ -274,9 +285,8 @@ wb_status wb_apply_A_lowp(const wb_mesh* mh, const wb_visc* vc, int prec, const 
       WB_HIP(hipMalloc(&v->mu_q_f, sizeof(float) * nq));
       launch_cast<double, float>(S(stream), nq, v->mu_q, v->mu_q_f);
     }
-    launch_fill<float>(S(stream), y, 0.0f, (size_t)3 * m.nn);
     launch_op<float>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q_f, nullptr, nullptr, nullptr,
-                     nullptr);
+                     false, mesh_work(mh));
     check_launch();
     return WB_OK;
   });
@@ -374,6 +384,20 @@ wb_status wb_solve(wb_solver* sh, const double* f, double* u, double* p, wb_repo
   });
 }
 
+wb_status wb_subsolve(wb_solver* sh, int which, const double* b, double* x, wb_report* rep,
+                      void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(which >= 0 && which <= 2, WB_EINVAL, "which must be 0 (A), 1 (K_l) or 2 (K_r)");
+    WB_REQUIRE(b && x && b != x, WB_EINVAL, "bad vectors");
+    s.st = S(stream);
+    wb_status r = subsolve(s, which, b, x, rep);
+    check_launch();
+    if (r == WB_ENOCONV) set_error("GMRES reached max_iter before rtol");
+    return r;
+  });
+}
+
 wb_status wb_solver_query(wb_solver* sh, int what, int level, double* out, void* stream) {
   return guard([&] {
     Solver& s = SV(sh);
@@ -449,7 +473,7 @@ wb_status wb_apply_A_add(const wb_mesh* mh, const wb_visc* v, const double* u, d
     WB_REQUIRE(u != y, WB_EINVAL, "in-place apply is not allowed");
     const Mesh& m = mh->m;
     launch_op<double>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q, nullptr, nullptr, nullptr,
-                      nullptr);
+                      true, mesh_work(mh));
     check_launch();
     return WB_OK;
   });

@@ -17,12 +17,16 @@ enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8 };
 
 // Sum-factorized element operator on a level with N elements/dir and order k.
 // NC = 3 (viscous stress, coef = mu) or 1 (scalar Poisson, coef = c).
-//   y   += op(u)   (y must be zeroed by the caller; atomics)       [NC][nn]
-//   pout = B u     (written)                                         [E][np]
-//   sin: optional per-node input scaling, sout: optional per-node output scaling.
+//   y    = op(u)  (or y += op(u) when add)  [NC][nn]; every node is written, no zeroing needed
+//   pout = B u   (written)                   [E][np]
+//   sin: optional per-node input scaling.
+// Operators that scatter to nodes run in two kernels: blocks own bricks of elements and
+// accumulate in LDS; values on internal brick faces pass through `work` (at least
+// op_workspace_bytes(NC, N, k, sizeof(T)) bytes) and are summed by a second kernel.
+size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size);
 template <typename T>
 void launch_op(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
-               const T* pin, T* pout, const T* sin, const T* sout);
+               const T* pin, T* pout, const T* sin, bool add, void* work);
 
 // Jacobi diagonal (not inverted) of the NC-component operator, accumulated into diag (zeroed).
 void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* coef, double* diag);

@@ -117,125 +117,174 @@ __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 inline unsigned grid_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // ------------------------------------------------------------------ operator
-template <int n, int NC, typename T, int F>
-__global__ void __launch_bounds__(256)
-k_op(const KT<n, T> tb, const int N, const int k, const int M, const int E, const int nn,
-     const T hh, const T* __restrict__ u, T* __restrict__ y, const T* __restrict__ coef,
-     const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ sin_,
-     const T* __restrict__ sout) {
-  constexpr int NN = n * n, N3 = n * n * n, EPB = 256 / NN;
-  constexpr int NP = (n - 1) * n * (n + 1) / 6;
-  __shared__ T sm[NC][EPB][N3];
-  const int t = threadIdx.x, le = t / NN, r = t - le * NN, i = r % n, j = r / n;
-  const int e = blockIdx.x * EPB + le;
-  const bool valid = e < E;
-  int ex = 0, ey = 0, ez = 0;
-  if (valid) {
-    ex = e % N;
-    const int q = e / N;
-    ey = q % N;
-    ez = q / N;
-  }
-  const int gi = ex * k + i, gj = ey * k + j;
-  const bool bij = (gi == 0) || (gi == M - 1) || (gj == 0) || (gj == M - 1);
+// All threads of one element live in one wavefront, so the exchanges inside an element need
+// only a wavefront-scope barrier (LDS operations of a wave complete in order).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-  T S[NC][3][n];
+// Elements per wavefront and the lane mapping: lane -> (element slot, thread in element).
+template <int n>
+struct WaveMap {
+  static constexpr int NN = n * n, EPW = 64 / NN;
+  static __device__ inline void map(int t, int& slot, int& r, bool& lane_ok) {
+    const int wave = t >> 6, lane = t & 63;
+    const int le = lane / NN;
+    lane_ok = le < EPW;
+    r = lane_ok ? lane - le * NN : 0;
+    slot = lane_ok ? wave * EPW + le : -1;
+  }
+};
+
+// 1D tables are centro-symmetric: B(n-1-q, n-1-l) = B(q, l) and Dh(n-1-q, n-1-m) = -Dh(q, m)
+// (symmetric Gauss points, symmetric GLL nodes); Dh vanishes at the middle of an odd rule.
+// Referencing only the first half of each table keeps the distinct constants (scalar
+// registers) at about half; the indices are compile-time after unrolling.
+template <int n, typename T>
+__device__ __forceinline__ T Bm(const KT<n, T>& tb, int q, int l) {
+  constexpr int H = n / 2;
+  if (q < H) return tb.B[q * n + l];
+  if (q >= n - H) return tb.B[(n - 1 - q) * n + (n - 1 - l)];
+  return tb.B[q * n + (l <= H ? l : n - 1 - l)];           // middle row of an odd rule
+}
+template <int n, typename T>
+__device__ __forceinline__ T Dm(const KT<n, T>& tb, int q, int m) {
+  constexpr int H = n / 2;
+  if (q < H) return tb.Dh[q * n + m];
+  if (q >= n - H) return -tb.Dh[(n - 1 - q) * n + (n - 1 - m)];
+  if (m == H) return T(0);
+  return m < H ? tb.Dh[q * n + m] : -tb.Dh[q * n + (n - 1 - m)];
+}
+
+// LDS layout of an element's scratch: value (x, y, z) at x + SY y + SZ z, slots SL apart.  The
+// strides keep the three line roles of a wavefront (z-, y- and x-lines) free of bank conflicts
+// beyond two-way (searched over padded strides for 64-lane ds_read_b64 access).
+template <int n> struct Lds;
+template <> struct Lds<2> { static constexpr int SY = 2, SZ = 4, SL = 8; };
+template <> struct Lds<3> { static constexpr int SY = 3, SZ = 9, SL = 27; };
+template <> struct Lds<4> { static constexpr int SY = 4, SZ = 18, SL = 71; };
+template <> struct Lds<5> { static constexpr int SY = 5, SZ = 25, SL = 125; };
+
+// Element computation shared by the operator kernels.  The n^2 lanes of an element take three
+// roles, always with a = r % n, b = r / n: the z-line (a, b, .), the y-line (a, ., b) or the
+// x-line (., a, b).  A lane contracts a whole line with compile-time table indices; lines move
+// between roles through the element's LDS scratch s, s2 (layout of Lds<n>).
+// Components are processed one after the other.  For F_A / F_BT the contribution of the
+// element to its local node (x, y, z) of component c is handed to sink(c, x, y, z, value);
+// F_B writes the element's n_p pressure modes to pout.
+// Contains wavefront barriers: every lane of the wavefront must call it.
+template <int n, int NC, typename T, int F, typename Sink>
+__device__ inline void element_op(const KT<n, T>& tb, const bool valid, const int e, const int ex,
+                                  const int ey, const int ez, const int k, const int M,
+                                  const int nn, const T hh, const T* __restrict__ u,
+                                  const T* __restrict__ coef, const T* __restrict__ pin,
+                                  T* __restrict__ pout, const T* __restrict__ sin_, T* s, T* s2,
+                                  const int r, Sink&& sink) {
+  constexpr int NN = n * n, N3 = n * n * n;
+  constexpr int NP = (n - 1) * n * (n + 1) / 6;
+  constexpr int SY = Lds<n>::SY, SZ = Lds<n>::SZ;
+  const int a = r % n, b = r / n;
+  // z-line role (i, j) = (a, b)
+  const int gi = ex * k + a, gj = ey * k + b;
+  const bool bij = (gi == 0) || (gi == M - 1) || (gj == 0) || (gj == M - 1);
+  T S[NC][3][n];  // z-line role: gradients, then stresses, at (a, b, q)
   T bq[n];
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int q = 0; q < n; ++q) S[c][d][q] = T(0);
 
   if constexpr ((F & (F_A | F_B)) != 0) {
-    T U[NC][n];
+    int gidx[n];
+    T sc[n];
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       const int gl = ez * k + l;
-      const int g = gi + M * (gj + M * gl);
+      gidx[l] = gi + M * (gj + M * gl);
       const bool bnd = (F & F_DIR) && (bij || gl == 0 || gl == M - 1);
-      T s = T(1);
-      if (sin_ != nullptr && valid) s = sin_[g];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) U[c][l] = (valid && !bnd) ? u[(size_t)c * nn + g] * s : T(0);
+      sc[l] = (valid && !bnd) ? ((sin_ != nullptr) ? sin_[gidx[l]] : T(1)) : T(0);
     }
-    // interpolation to Gauss points: z in registers
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      T tmp[n];
+      T v[n], w[n];
+      // z: interpolate the node column to the Gauss points
+#pragma unroll
+      for (int l = 0; l < n; ++l) v[l] = sc[l] != T(0) ? u[(size_t)c * nn + gidx[l]] * sc[l] : T(0);
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        T a = T(0);
+        T acc = T(0);
 #pragma unroll
-        for (int l = 0; l < n; ++l) a += tb.B[q * n + l] * U[c][l];
-        tmp[q] = a;
+        for (int l = 0; l < n; ++l) acc += Bm(tb, q, l) * v[l];
+        s[a + SY * b + SZ * q] = acc;
+      }
+      wave_sync();
+      // y-line (a, ., b): interpolate in y, in place
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Bm(tb, q, m) * v[m];
+        s[a + SY * q + SZ * b] = acc;
+      }
+      wave_sync();
+      // x-line (., a, b): interpolate in x, then differentiate in x
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Bm(tb, q, m) * v[m];
+        w[q] = acc;
       }
 #pragma unroll
-      for (int q = 0; q < n; ++q) U[c][q] = tmp[q];
+      for (int q = 0; q < n; ++q) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Dm(tb, q, m) * w[m];
+        s[q + SY * a + SZ * b] = w[q];
+        s2[q + SY * a + SZ * b] = acc;
+      }
+      wave_sync();
+      // y-line: differentiate in y (kept); z-line: differentiate in z
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Dm(tb, q, m) * v[m];
+        w[q] = acc;
+      }
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = s[a + SY * b + SZ * m];
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Dm(tb, q, m) * v[m];
+        S[c][2][q] = acc;
+      }
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < n; ++q) s[a + SY * q + SZ * b] = w[q];
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        S[c][0][q] = s2[a + SY * b + SZ * q];
+        S[c][1][q] = s[a + SY * b + SZ * q];
+      }
+      wave_sync();
     }
-    // y
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) sm[c][le][q * NN + j * n + i] = U[c][q];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T a = T(0);
-#pragma unroll
-        for (int b = 0; b < n; ++b) a += tb.B[j * n + b] * sm[c][le][q * NN + b * n + i];
-        U[c][q] = a;
-      }
-    __syncthreads();
-    // x
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) sm[c][le][q * NN + j * n + i] = U[c][q];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T a = T(0);
-#pragma unroll
-        for (int b = 0; b < n; ++b) a += tb.B[i * n + b] * sm[c][le][q * NN + j * n + b];
-        U[c][q] = a;
-      }
-    __syncthreads();
-    // collocation derivatives at the Gauss points
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) sm[c][le][q * NN + j * n + i] = U[c][q];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T gx = T(0), gy = T(0), gz = T(0);
-#pragma unroll
-        for (int b = 0; b < n; ++b) {
-          gx += tb.Dh[i * n + b] * sm[c][le][q * NN + j * n + b];
-          gy += tb.Dh[j * n + b] * sm[c][le][q * NN + b * n + i];
-          gz += tb.Dh[q * n + b] * U[c][b];
-        }
-        S[c][0][q] = gx;
-        S[c][1][q] = gy;
-        S[c][2][q] = gz;
-      }
-    __syncthreads();
-    // pointwise
+    // pointwise at (a, b, q)
+    const T wab = tb.w[a] * tb.w[b];
 #pragma unroll
     for (int q = 0; q < n; ++q) {
-      const T w3 = tb.w[i] * tb.w[j] * tb.w[q];
+      const T w3 = wab * tb.w[q];
       if constexpr (NC == 3) {
         if constexpr ((F & F_B) != 0) bq[q] = -hh * hh * w3 * (S[0][0][q] + S[1][1][q] + S[2][2][q]);
         if constexpr ((F & F_A) != 0) {
-          const T cw = valid ? coef[(size_t)e * N3 + q * NN + j * n + i] * w3 * hh : T(0);
+          const T cw = valid ? coef[(size_t)e * N3 + q * NN + b * n + a] * w3 * hh : T(0);
           const T s01 = cw * (S[0][1][q] + S[1][0][q]);
           const T s02 = cw * (S[0][2][q] + S[2][0][q]);
           const T s12 = cw * (S[1][2][q] + S[2][1][q]);
@@ -252,194 +301,460 @@ k_op(const KT<n, T> tb, const int N, const int k, const int M, const int E, cons
             for (int d = 0; d < 3; ++d) S[c][d][q] = T(0);
         }
       } else {
-        const T cw = valid ? coef[(size_t)e * N3 + q * NN + j * n + i] * w3 * hh : T(0);
+        const T cw = valid ? coef[(size_t)e * N3 + q * NN + b * n + a] * w3 * hh : T(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) S[0][d][q] *= cw;
       }
     }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < n; ++q) S[c][d][q] = T(0);
   }
 
   if constexpr (NC == 3 && (F & F_B) != 0) {
     // project -(h/2)^2 w3 div u onto the Legendre modes
 #pragma unroll
     for (int c = 0; c < n - 1; ++c) {
-      T a = T(0);
+      T acc = T(0);
 #pragma unroll
-      for (int q = 0; q < n; ++q) a += tb.L[c * n + q] * bq[q];
-      sm[0][le][c * NN + j * n + i] = a;
+      for (int q = 0; q < n; ++q) acc += tb.L[c * n + q] * bq[q];
+      s[a + SY * b + SZ * c] = acc;
     }
-    __syncthreads();
+    wave_sync();
     if (valid && r < NP) {
-      const int a = tb.ma[r], b = tb.mb[r], c = tb.mc[r];
-      T s = T(0);
+      const int ma = tb.ma[r], mb = tb.mb[r], mc = tb.mc[r];
+      T acc = T(0);
 #pragma unroll
       for (int jj = 0; jj < n; ++jj)
 #pragma unroll
         for (int ii = 0; ii < n; ++ii)
-          s += tb.L[a * n + ii] * tb.L[b * n + jj] * sm[0][le][c * NN + jj * n + ii];
-      pout[(size_t)e * NP + r] = s;
+          acc += tb.L[ma * n + ii] * tb.L[mb * n + jj] * s[ii + SY * jj + SZ * mc];
+      pout[(size_t)e * NP + r] = acc;
     }
-    __syncthreads();
+    wave_sync();
   }
 
   if constexpr (NC == 3 && (F & F_BT) != 0) {
-    T pm[NP];
+    T La[n - 1], Lb[n - 1];
 #pragma unroll
-    for (int m = 0; m < NP; ++m) pm[m] = valid ? pin[(size_t)e * NP + m] : T(0);
+    for (int m = 0; m < n - 1; ++m) {
+      La[m] = tb.L[m * n + a];
+      Lb[m] = tb.L[m * n + b];
+    }
+    const T wab = tb.w[a] * tb.w[b];
 #pragma unroll
     for (int q = 0; q < n; ++q) {
       T pq = T(0);
 #pragma unroll
-      for (int m = 0; m < NP; ++m)
-        pq += pm[m] * tb.L[tb.ma[m] * n + i] * tb.L[tb.mb[m] * n + j] * tb.L[tb.mc[m] * n + q];
-      const T v = -hh * hh * tb.w[i] * tb.w[j] * tb.w[q] * pq;
-      S[0][0][q] += v;
-      S[1][1][q] += v;
-      S[2][2][q] += v;
+      for (int m = 0; m < NP; ++m) {
+        const T pmv = valid ? pin[(size_t)e * NP + m] : T(0);
+        pq += pmv * La[tb.ma[m]] * Lb[tb.mb[m]] * tb.L[tb.mc[m] * n + q];
+      }
+      const T vv = -hh * hh * wab * tb.w[q] * pq;
+      S[0][0][q] += vv;
+      S[1][1][q] += vv;
+      S[2][2][q] += vv;
     }
   }
 
   if constexpr ((F & (F_A | F_BT)) != 0) {
-    T V[NC][n];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T a = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) a += tb.Dh[m * n + q] * S[c][2][m];
-        V[c][q] = a;
-      }
-    // x-derivative transpose
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) sm[c][le][q * NN + j * n + i] = S[c][0][q];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      T V[n], v[n];
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        T a = T(0);
+        T acc = T(0);
 #pragma unroll
-        for (int b = 0; b < n; ++b) a += tb.Dh[b * n + i] * sm[c][le][q * NN + j * n + b];
-        V[c][q] += a;
+        for (int m = 0; m < n; ++m) acc += Dm(tb, m, q) * S[c][2][m];
+        V[q] = acc;
+        s[a + SY * b + SZ * q] = S[c][0][q];
+        s2[a + SY * b + SZ * q] = S[c][1][q];
       }
-    __syncthreads();
-    // y-derivative transpose
+      wave_sync();
+      // x-line: transposed x-derivative of S_cx; y-line: transposed y-derivative of S_cy
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) sm[c][le][q * NN + j * n + i] = S[c][1][q];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        T a = T(0);
+        T acc = T(0);
 #pragma unroll
-        for (int b = 0; b < n; ++b) a += tb.Dh[b * n + j] * sm[c][le][q * NN + b * n + i];
-        V[c][q] += a;
+        for (int m = 0; m < n; ++m) acc += Dm(tb, m, q) * v[m];
+        s[q + SY * a + SZ * b] = acc;
       }
-    __syncthreads();
-    // x interpolation transpose
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < n; ++q) sm[c][le][q * NN + j * n + i] = V[c][q];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int m = 0; m < n; ++m) v[m] = s2[a + SY * m + SZ * b];
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        T a = T(0);
+        T acc = T(0);
 #pragma unroll
-        for (int b = 0; b < n; ++b) a += tb.B[b * n + i] * sm[c][le][q * NN + j * n + b];
-        V[c][q] = a;
+        for (int m = 0; m < n; ++m) acc += Dm(tb, m, q) * v[m];
+        s2[a + SY * q + SZ * b] = acc;
       }
-    __syncthreads();
-    // y interpolation transpose
+      wave_sync();
+      // z-line: sum, then transposed z-interpolation to the nodes
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int q = 0; q < n; ++q) V[q] += s[a + SY * b + SZ * q] + s2[a + SY * b + SZ * q];
+      wave_sync();
 #pragma unroll
-      for (int q = 0; q < n; ++q) sm[c][le][q * NN + j * n + i] = V[c][q];
-    __syncthreads();
+      for (int l = 0; l < n; ++l) {
+        T acc = T(0);
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+        for (int q = 0; q < n; ++q) acc += Bm(tb, q, l) * V[q];
+        s[a + SY * b + SZ * l] = acc;
+      }
+      wave_sync();
+      // y-line (a, ., b = z node): transposed y-interpolation, in place
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        T a = T(0);
+        T acc = T(0);
 #pragma unroll
-        for (int b = 0; b < n; ++b) a += tb.B[b * n + j] * sm[c][le][q * NN + b * n + i];
-        V[c][q] = a;
+        for (int m = 0; m < n; ++m) acc += Bm(tb, m, q) * v[m];
+        s[a + SY * q + SZ * b] = acc;
       }
-    // z interpolation transpose and scatter
+      wave_sync();
+      // x-line (., a = y node, b = z node): transposed x-interpolation to the nodes
 #pragma unroll
-    for (int l = 0; l < n; ++l) {
-      const int gl = ez * k + l;
-      const int g = gi + M * (gj + M * gl);
-      const bool bnd = (F & F_DIR) && (bij || gl == 0 || gl == M - 1);
-      if (valid && !bnd) {
-        T s = T(1);
-        if (sout != nullptr) s = sout[g];
+      for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T a = T(0);
+      for (int q = 0; q < n; ++q) {
+        T acc = T(0);
 #pragma unroll
-          for (int q = 0; q < n; ++q) a += tb.B[q * n + l] * V[c][q];
-          atomic_add(&y[(size_t)c * nn + g], a * s);
-        }
+        for (int m = 0; m < n; ++m) acc += Bm(tb, m, q) * v[m];
+        sink(c, q, a, b, acc);
       }
+      wave_sync();
     }
   }
 }
 
+// Divergence only (no scatter): element-parallel, writes the pressure modes.
+template <int n, typename T, int F>
+__global__ void __launch_bounds__(256)
+k_op_gather(const KT<n, T> tb, const int N, const int k, const int M, const int E, const int nn,
+            const T hh, const T* __restrict__ u, const T* __restrict__ pout_unused,
+            T* __restrict__ pout, const T* __restrict__ sin_) {
+  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n>::SL;
+  __shared__ T sm[2 * (SLOTS + 1) * SL];
+  int slot, r;
+  bool lane_ok;
+  WaveMap<n>::map(threadIdx.x, slot, r, lane_ok);
+  const int e = blockIdx.x * SLOTS + slot;
+  const bool valid = lane_ok && e < E;
+  int ex = 0, ey = 0, ez = 0;
+  if (valid) {
+    ex = e % N;
+    const int q = e / N;
+    ey = q % N;
+    ez = q / N;
+  }
+  T* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
+  element_op<n, 3, T, F>(tb, valid, e, ex, ey, ez, k, M, nn, hh, u, nullptr, nullptr, pout, sin_, s0,
+                         s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
+}
+
+// Brick geometry of the scatter kernel: a block owns a BX x BY tile of elements and marches
+// through a chunk of Bz element layers in z.
+template <int n> struct Tile;
+template <> struct Tile<2> { static constexpr int BX = 8, BY = 8; };
+template <> struct Tile<3> { static constexpr int BX = 8, BY = 4; };
+template <> struct Tile<4> { static constexpr int BX = 8, BY = 4; };
+template <> struct Tile<5> { static constexpr int BX = 4, BY = 4; };
+
+struct BrickGeom {
+  int N, k, M, nn, E;
+  int BX, BY, Bz;        // tile and chunk sizes (elements)
+  int nbx, nby, nbz;     // bricks per direction
+  size_t plane;          // M * M
+  size_t fx, fy, fz;     // offsets (elements of T) of the x/y/z face arrays per component
+  size_t per_comp;       // face-array elements per component
+};
+
+inline BrickGeom brick_geom(int N, int k, int BX, int BY) {
+  BrickGeom g;
+  g.N = N;
+  g.k = k;
+  g.M = k * N + 1;
+  g.nn = g.M * g.M * g.M;
+  g.E = N * N * N;
+  g.BX = BX;
+  g.BY = BY;
+  g.nbx = (N + BX - 1) / BX;
+  g.nby = (N + BY - 1) / BY;
+  const int tiles = g.nbx * g.nby;
+  g.Bz = std::max(2, std::min(N, (N * tiles) / 512));
+  g.nbz = (N + g.Bz - 1) / g.Bz;
+  g.plane = (size_t)g.M * g.M;
+  g.fx = 0;
+  g.fy = 8 * (size_t)(g.nbx - 1) * g.plane;
+  g.fz = g.fy + 8 * (size_t)(g.nby - 1) * g.plane;
+  g.per_comp = g.fz + 8 * (size_t)(g.nbz - 1) * g.plane;
+  return g;
+}
+
+// Store one finished node value: direct when the node is owned by this brick alone, else into
+// the face array of the first internal brick plane it lies on, slot s = sx + 2 sy + 4 sz
+// (s_d = 1 when this brick lies above that plane).
+template <int NC, typename T, bool DIR>
+__device__ inline void store_node(const BrickGeom& G, const int gx, const int gy, const int gz,
+                                  const int X0, const int Y0, const int Z0, const int X1,
+                                  const int Y1, const int Z1, const T (&val)[NC],
+                                  T* __restrict__ y, T* __restrict__ face, const int add) {
+  const int M = G.M;
+  const size_t g = (size_t)gx + (size_t)M * (gy + (size_t)M * gz);
+  if (DIR && (gx == 0 || gx == M - 1 || gy == 0 || gy == M - 1 || gz == 0 || gz == M - 1)) {
+    if (!add)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) y[(size_t)c * G.nn + g] = T(0);
+    return;
+  }
+  const bool lx = gx == X0 && X0 > 0, ux = gx == X1 && X1 < M - 1;
+  const bool ly = gy == Y0 && Y0 > 0, uy = gy == Y1 && Y1 < M - 1;
+  const bool lz = gz == Z0 && Z0 > 0, uz = gz == Z1 && Z1 < M - 1;
+  if (!(lx || ux || ly || uy || lz || uz)) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T* p = &y[(size_t)c * G.nn + g];
+      *p = add ? *p + val[c] : val[c];
+    }
+    return;
+  }
+  const int s = (lx ? 1 : 0) + 2 * (ly ? 1 : 0) + 4 * (lz ? 1 : 0);
+  size_t off;
+  if (lx || ux) {
+    const int b = gx / (G.k * G.BX) - 1;
+    off = G.fx + ((size_t)(s * (G.nbx - 1) + b) * M + gz) * M + gy;
+  } else if (ly || uy) {
+    const int b = gy / (G.k * G.BY) - 1;
+    off = G.fy + ((size_t)(s * (G.nby - 1) + b) * M + gz) * M + gx;
+  } else {
+    const int b = gz / (G.k * G.Bz) - 1;
+    off = G.fz + ((size_t)(s * (G.nbz - 1) + b) * M + gy) * M + gx;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) face[(size_t)c * G.per_comp + off] = val[c];
+}
+
+// Scatter operator: y = op(u) (or y += op(u)), F_B output as well when requested.
+template <int n>
+struct BrickThreads {
+  static constexpr int NE = Tile<n>::BX * Tile<n>::BY;
+  static constexpr int WAVES = (NE + WaveMap<n>::EPW - 1) / WaveMap<n>::EPW;
+  static constexpr int NT = 64 * WAVES;
+};
+
+template <int n, int NC, typename T, int F>
+__global__ void __launch_bounds__(BrickThreads<n>::NT)
+k_op_brick(const KT<n, T> tb, const BrickGeom G, const T hh, const T* __restrict__ u,
+           T* __restrict__ y, const T* __restrict__ coef, const T* __restrict__ pin,
+           T* __restrict__ pout, const T* __restrict__ sin_, T* __restrict__ face, const int add) {
+  constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY, NE = BX * BY;
+  constexpr int N3 = n * n * n, k = n - 1;
+  constexpr int WX = k * BX + 1, WY = k * BY + 1, WP = WX * WY;   // window plane
+  constexpr int NT = BrickThreads<n>::NT, SLOTS = BrickThreads<n>::WAVES * WaveMap<n>::EPW;
+  constexpr int SL = Lds<n>::SL;
+  __shared__ T sm[2 * (SLOTS + 1) * SL];
+  __shared__ T win[NC * (k + 1) * WP];
+  const int N = G.N, M = G.M;
+  const int t = threadIdx.x;
+  int le, r;
+  bool lane_ok;
+  WaveMap<n>::map(t, le, r, lane_ok);
+  const bool slot_ok = lane_ok && le < NE;
+  const int lx = slot_ok ? le % BX : 0, ly = slot_ok ? le / BX : 0;
+  const int tx = blockIdx.x % G.nbx, ty = blockIdx.x / G.nbx, bz = blockIdx.y;
+  const int ex = tx * BX + lx, ey = ty * BY + ly;
+  const int X0 = tx * BX * k, Y0 = ty * BY * k;
+  const int X1 = X0 + k * BX, Y1 = Y0 + k * BY;
+  const int ez0 = bz * G.Bz, ez1 = min(N, ez0 + G.Bz);
+  const int Z0 = ez0 * k, Z1 = ez1 * k;
+  for (int idx = t; idx < NC * (k + 1) * WP; idx += NT) win[idx] = T(0);
+  __syncthreads();
+  for (int ez = ez0; ez < ez1; ++ez) {
+    const bool valid = slot_ok && ex < N && ey < N;
+    const int e = ex + N * (ey + N * ez);
+    T* wbase = win + (ly * k) * WX + lx * k;
+    T* s0 = sm + (lane_ok ? le : SLOTS) * SL;
+    element_op<n, NC, T, F>(tb, valid, e, ex, ey, ez, k, M, G.nn, hh, u, coef, pin, pout, sin_, s0,
+                            s0 + (SLOTS + 1) * SL, r, [&](int c, int x, int yy, int z, T v) {
+                              if (valid) atomicAdd(wbase + (c * (k + 1) + z) * WP + yy * WX + x, v);
+                            });
+    __syncthreads();
+    // planes z = ez k .. ez k + k - 1 are complete
+    for (int idx = t; idx < k * WP; idx += NT) {
+      const int l = idx / WP, w = idx - l * WP;
+      const int wx = w % WX, wy = w / WX;
+      const int gx = X0 + wx, gy = Y0 + wy, gz = ez * k + l;
+      if (gx >= M || gy >= M) continue;
+      T val[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1) + l) * WP + w];
+      store_node<NC, T, (F & F_DIR) != 0>(G, gx, gy, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add);
+    }
+    __syncthreads();
+    // shift the window: plane k becomes plane 0, the others restart at zero
+    for (int idx = t; idx < NC * WP; idx += NT) {
+      const int c = idx / WP, w = idx - c * WP;
+      win[(c * (k + 1)) * WP + w] = win[(c * (k + 1) + k) * WP + w];
+#pragma unroll
+      for (int l = 1; l <= k; ++l) win[(c * (k + 1) + l) * WP + w] = T(0);
+    }
+    __syncthreads();
+  }
+  // last plane of the chunk (z = Z1)
+  for (int w = t; w < WP; w += NT) {
+    const int wx = w % WX, wy = w / WX;
+    const int gx = X0 + wx, gy = Y0 + wy;
+    if (gx >= M || gy >= M) continue;
+    T val[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1)) * WP + w];
+    store_node<NC, T, (F & F_DIR) != 0>(G, gx, gy, Z1, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add);
+  }
+}
+
+// Sum the partial values on internal brick planes into y (x planes, then y planes not on an
+// x plane, then z planes on neither).
+template <int NC, typename T, bool DIR>
+__global__ void k_face_sum(const BrickGeom G, const T* __restrict__ face, T* __restrict__ y,
+                           const int add) {
+  const int M = G.M;
+  const long long nx = (long long)(G.nbx - 1) * M * M, ny = (long long)(G.nby - 1) * M * M;
+  const long long nz = (long long)(G.nbz - 1) * M * M;
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nx + ny + nz) return;
+  const int KX = G.k * G.BX, KY = G.k * G.BY, KZ = G.k * G.Bz;
+  int gx, gy, gz, cat, b;
+  if (idx < nx) {
+    cat = 0;
+    b = (int)(idx / ((long long)M * M));
+    const long long rem = idx % ((long long)M * M);
+    gz = (int)(rem / M);
+    gy = (int)(rem % M);
+    gx = (b + 1) * KX;
+  } else if (idx < nx + ny) {
+    idx -= nx;
+    cat = 1;
+    b = (int)(idx / ((long long)M * M));
+    const long long rem = idx % ((long long)M * M);
+    gz = (int)(rem / M);
+    gx = (int)(rem % M);
+    gy = (b + 1) * KY;
+  } else {
+    idx -= nx + ny;
+    cat = 2;
+    b = (int)(idx / ((long long)M * M));
+    const long long rem = idx % ((long long)M * M);
+    gy = (int)(rem / M);
+    gx = (int)(rem % M);
+    gz = (b + 1) * KZ;
+  }
+  const bool on_x = gx % KX == 0 && gx > 0 && gx < M - 1;
+  const bool on_y = gy % KY == 0 && gy > 0 && gy < M - 1;
+  const bool on_z = gz % KZ == 0 && gz > 0 && gz < M - 1;
+  if (cat == 1 && on_x) return;
+  if (cat == 2 && (on_x || on_y)) return;
+  if (DIR && (gx == 0 || gx == M - 1 || gy == 0 || gy == M - 1 || gz == 0 || gz == M - 1)) return;
+  T val[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) val[c] = T(0);
+  for (int sz = 0; sz <= (on_z ? 1 : 0); ++sz)
+    for (int sy = 0; sy <= (on_y ? 1 : 0); ++sy)
+      for (int sx = 0; sx <= (on_x ? 1 : 0); ++sx) {
+        const int s = sx + 2 * sy + 4 * sz;
+        size_t off;
+        if (cat == 0) off = G.fx + ((size_t)(s * (G.nbx - 1) + b) * M + gz) * M + gy;
+        else if (cat == 1) off = G.fy + ((size_t)(s * (G.nby - 1) + b) * M + gz) * M + gx;
+        else off = G.fz + ((size_t)(s * (G.nbz - 1) + b) * M + gy) * M + gx;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) val[c] += face[(size_t)c * G.per_comp + off];
+      }
+  const size_t g = (size_t)gx + (size_t)M * (gy + (size_t)M * gz);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    T* p = &y[(size_t)c * G.nn + g];
+    *p = add ? *p + val[c] : val[c];
+  }
+}
+
+struct ProfScope {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t st;
+  std::string key;
+  ProfScope(hipStream_t s, std::string k) : st(s), key(std::move(k)) {
+    if (!prof::on) return;
+    std::lock_guard<std::mutex> g(prof::mu);
+    a = prof::get_event();
+    b = prof::get_event();
+    if (a) (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a || !b) return;
+    std::lock_guard<std::mutex> g(prof::mu);
+    (void)hipEventRecord(b, st);
+    prof::recs.push_back({key, a, b});
+  }
+};
+
+std::string op_key(int NC, int k, int N, int F, bool scale, size_t es, const char* part) {
+  char key[160];
+  snprintf(key, sizeof(key), "op%s nc=%d k=%d N=%d flags=%s%s%s%s%s %s", part, NC, k, N,
+           (F & F_A) ? "A" : "", (F & F_BT) ? "+BT" : "", (F & F_B) ? "+B" : "",
+           (F & F_DIR) ? "+dir" : "", scale ? "+scale" : "", es == 8 ? "f64" : "f32");
+  return key;
+}
+
 template <int n, int NC, typename T, int F>
 void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, const T* pin, T* pout,
-               const T* sin, const T* sout) {
-  constexpr int NN = n * n, EPB = 256 / NN;
+               const T* sin, bool add, void* work) {
   const int M = k * N + 1, E = N * N * N, nn = M * M * M;
   const T hh = (T)(0.5 / N);
   const KT<n, T> tb = make_kt<n, T>(k);
-  hipEvent_t ea = nullptr, eb = nullptr;
-  if (prof::on) {
-    std::lock_guard<std::mutex> g(prof::mu);
-    ea = prof::get_event();
-    eb = prof::get_event();
-    if (ea) (void)hipEventRecord(ea, st);
-  }
-  hipLaunchKernelGGL((k_op<n, NC, T, F>), dim3(grid_for(E, EPB)), dim3(EPB * NN), 0, st, tb, N, k,
-                     M, E, nn, hh, u, y, coef, pin, pout, sin, sout);
-  if (ea && eb) {
-    std::lock_guard<std::mutex> g(prof::mu);
-    (void)hipEventRecord(eb, st);
-    char key[160];
-    snprintf(key, sizeof(key), "op nc=%d k=%d N=%d flags=%s%s%s%s%s %s", NC, k, N,
-             (F & F_A) ? "A" : "", (F & F_BT) ? "+BT" : "", (F & F_B) ? "+B" : "",
-             (F & F_DIR) ? "+dir" : "", sin ? "+scale" : "", sizeof(T) == 8 ? "f64" : "f32");
-    prof::recs.push_back({key, ea, eb});
+  if constexpr ((F & (F_A | F_BT)) == 0) {
+    constexpr int SLOTS = 4 * WaveMap<n>::EPW;
+    ProfScope ps(st, op_key(NC, k, N, F, sin != nullptr, sizeof(T), ""));
+    hipLaunchKernelGGL((k_op_gather<n, T, F>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, tb, N, k,
+                       M, E, nn, hh, u, nullptr, pout, sin);
+  } else {
+    constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY;
+    const BrickGeom G = brick_geom(N, k, BX, BY);
+    T* face = static_cast<T*>(work);
+    {
+      ProfScope ps(st, op_key(NC, k, N, F, sin != nullptr, sizeof(T), ""));
+      hipLaunchKernelGGL((k_op_brick<n, NC, T, F>), dim3(G.nbx * G.nby, G.nbz),
+                         dim3(BrickThreads<n>::NT), 0, st, tb, G, hh, u, y, coef, pin, pout, sin,
+                         face, (int)add);
+    }
+    const size_t tot = (size_t)(G.nbx + G.nby + G.nbz - 3) * G.plane;
+    if (tot > 0) {
+      ProfScope ps(st, op_key(NC, k, N, F, sin != nullptr, sizeof(T), "-faces"));
+      hipLaunchKernelGGL((k_face_sum<NC, T, (F & F_DIR) != 0>), dim3(grid_for(tot, 256)), dim3(256),
+                         0, st, G, face, y, (int)add);
+    }
   }
 }
 
 template <int n, typename T>
 void op_dispatch_n(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
-                   const T* pin, T* pout, const T* sin, const T* sout) {
+                   const T* pin, T* pout, const T* sin, bool add, void* work) {
   if (NC == 1) {
-    if (flags == F_A)
-      return op_launch<n, 1, T, F_A>(st, N, k, u, y, coef, pin, pout, sin, sout);
-    if (flags == (F_A | F_DIR))
-      return op_launch<n, 1, T, F_A | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, sout);
+    if (flags == F_A) return op_launch<n, 1, T, F_A>(st, N, k, u, y, coef, pin, pout, sin, add, work);
   } else {
     switch (flags) {
       case F_A | F_DIR:
-        return op_launch<n, 3, T, F_A | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, sout);
+        return op_launch<n, 3, T, F_A | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, add, work);
       case F_A | F_BT | F_B | F_DIR:
         return op_launch<n, 3, T, F_A | F_BT | F_B | F_DIR>(st, N, k, u, y, coef, pin, pout, sin,
-                                                             sout);
+                                                             add, work);
       case F_B | F_DIR:
-        return op_launch<n, 3, T, F_B | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, sout);
+        return op_launch<n, 3, T, F_B | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, add, work);
       case F_BT | F_DIR:
-        return op_launch<n, 3, T, F_BT | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, sout);
+        return op_launch<n, 3, T, F_BT | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, add, work);
       default:
         break;
     }
@@ -875,21 +1190,34 @@ __global__ void k_gemv(size_t n, int nv, const double* __restrict__ V, size_t ld
 }  // namespace
 
 // ================================================================== launchers
+size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size) {
+  int BX = 8, BY = 8;
+  switch (k + 1) {
+    case 2: BX = Tile<2>::BX; BY = Tile<2>::BY; break;
+    case 3: BX = Tile<3>::BX; BY = Tile<3>::BY; break;
+    case 4: BX = Tile<4>::BX; BY = Tile<4>::BY; break;
+    case 5: BX = Tile<5>::BX; BY = Tile<5>::BY; break;
+    default: break;
+  }
+  const BrickGeom G = brick_geom(N, k, BX, BY);
+  return elem_size * NC * std::max<size_t>(G.per_comp, 1);
+}
+
 template <typename T>
 void launch_op(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
-               const T* pin, T* pout, const T* sin, const T* sout) {
+               const T* pin, T* pout, const T* sin, bool add, void* work) {
   switch (k + 1) {
-    case 2: return op_dispatch_n<2, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, sout);
-    case 3: return op_dispatch_n<3, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, sout);
-    case 4: return op_dispatch_n<4, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, sout);
-    case 5: return op_dispatch_n<5, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, sout);
+    case 2: return op_dispatch_n<2, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
+    case 3: return op_dispatch_n<3, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
+    case 4: return op_dispatch_n<4, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
+    case 5: return op_dispatch_n<5, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
     default: throw Error{WB_EUNSUPPORTED, "order not built"};
   }
 }
 template void launch_op<double>(hipStream_t, int, int, int, int, const double*, double*,
-                                const double*, const double*, double*, const double*, const double*);
+                                const double*, const double*, double*, const double*, bool, void*);
 template void launch_op<float>(hipStream_t, int, int, int, int, const float*, float*, const float*,
-                               const float*, float*, const float*, const float*);
+                               const float*, float*, const float*, bool, void*);
 
 #define WB_BY_ORDER(k, ...)                                       \
   switch ((k) + 1) {                                              \

@@ -47,8 +47,9 @@ struct Hierarchy {
   int* gidx = nullptr;     // dense index -> vector index
 };
 
-// The (k, N) level schedule: halve k to 1, then halve N while N/2 >= 4.
-std::vector<std::pair<int, int>> level_schedule(int N, int k);
+// The (N, k) level schedule: lower k to 1 (halving, or by one when p_schedule == 1), then
+// halve N while N/2 >= 4.
+std::vector<std::pair<int, int>> level_schedule(int N, int k, int p_schedule);
 
 struct Solver;
 
@@ -75,6 +76,7 @@ struct Solver {
   double* mu_q = nullptr;   // fine viscosity (FP64)
   std::unique_ptr<Precond<double>> pd;
   std::unique_ptr<Precond<float>> pf;
+  void* opwork = nullptr;         // face-array workspace shared by all operator applies
   double* red_partial = nullptr;  // reduction scratch
   double* red_out = nullptr;      // [8] device scalars
   // Krylov space
@@ -106,6 +108,8 @@ void apply_precond(Solver& s, Precond<T>& P, const T* ru, const T* rp, T* zu, T*
 void apply_precond_any(Solver& s, const double* ru, const double* rp, double* zu, double* zp);
 
 wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep);
+// GMRES on one block with its V-cycle: which = 0 (A u = f), 1 (K_l p = g), 2 (K_r p = g).
+wb_status subsolve(Solver& s, int which, const double* b, double* x, wb_report* rep);
 
 // host helpers
 double dot_host(Solver& s, size_t n, const double* x, const double* y);

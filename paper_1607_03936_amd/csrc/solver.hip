@@ -25,10 +25,10 @@ void* Arena::raw(size_t bytes) {
   return p;
 }
 
-std::vector<std::pair<int, int>> level_schedule(int N, int k) {
+std::vector<std::pair<int, int>> level_schedule(int N, int k, int p_schedule) {
   std::vector<std::pair<int, int>> out{{N, k}};
   while (k > 1) {
-    k = std::max(1, k / 2);
+    k = p_schedule == 1 ? k - 1 : std::max(1, k / 2);
     out.push_back({N, k});
   }
   while (N % 2 == 0 && N / 2 >= 4) {
@@ -216,10 +216,9 @@ std::vector<double> make_bhat(int k) {
 }
 
 template <typename T>
-void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out) {
-  launch_fill<T>(st, out, T(0), L.len);
+void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out, void* work) {
   launch_op<T>(st, L.dir ? (F_A | F_DIR) : F_A, L.NC, L.N, L.k, in, out, L.coef, nullptr, nullptr,
-               nullptr, nullptr);
+               nullptr, false, work);
 }
 
 // Chebyshev-accelerated Jacobi (degree steps) for A x = b, A given as a callback.
@@ -280,7 +279,7 @@ double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, cons
 void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef0, int seed_base) {
   hipStream_t st = s.st;
   Arena& ar = s.arena;
-  auto sched = level_schedule(s.m.N, s.m.k);
+  auto sched = level_schedule(s.m.N, s.m.k, s.o.p_schedule);
   const int nl = (int)sched.size();
   H.L.resize(nl);
   for (int li = 0; li < nl; ++li) {
@@ -341,7 +340,7 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
       mean /= (double)b0.size();
       for (double& v : b0) v -= mean;
     }
-    auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out); };
+    auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out, s.opwork); };
     const double lam = lanczos_max(s, op, L.len, L.dinv, b0, s.o.lanczos_steps, L.x, L.b, L.r, L.d);
     L.lmin = 0.1 * lam;
     L.lmax = 1.1 * lam;
@@ -363,7 +362,7 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     launch_fill<double>(st, C.x, 0.0, C.len);
     const double one = 1.0;
     WB_HIP(hipMemcpyAsync(C.x + idx[j], &one, sizeof(double), hipMemcpyHostToDevice, st));
-    level_op<double>(st, C, C.x, C.t);
+    level_op<double>(st, C, C.x, C.t, s.opwork);
     WB_HIP(hipMemcpyAsync(col.data(), C.t, sizeof(double) * C.len, hipMemcpyDeviceToHost, st));
     WB_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < nd; ++i) Ad[(size_t)i * nd + j] = col[idx[i]];
@@ -471,7 +470,7 @@ void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
     launch_dense<T>(st, H.nd, H.G, H.gidx, b, x);
     return;
   }
-  auto op = [&](const T* in, T* out) { level_op<T>(st, L, in, out); };
+  auto op = [&](const T* in, T* out) { level_op<T>(st, L, in, out, s.opwork); };
   const int deg = s.o.cheb_degree;
   chebyshev<T>(st, op, L.len, L.dinv, L.lmin, L.lmax, deg, b, x, true, L.r, L.d, L.t);
   op(x, L.t);
@@ -492,9 +491,9 @@ template <typename T>
 void apply_K(Solver& s, Precond<T>& P, int side, const T* p, T* y) {
   hipStream_t st = s.st;
   const Mesh& m = s.m;
-  launch_fill<T>(st, P.vt, T(0), (size_t)3 * m.nn);
-  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr, nullptr, nullptr);
-  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y, P.winv[side],
+  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr, nullptr, false,
+               s.opwork);
+  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y, P.winv[side], false,
                nullptr);
 }
 
@@ -529,12 +528,12 @@ void apply_wbfbt(Solver& s, Precond<T>& P, const T* r, T* z) {
   launch_remove_mean<T>(st, m.E, m.np, P.pb, s.red_partial, s.red_out + 2);
   apply_vcycle_K<T>(s, P, 1, P.pb, P.py);
   // middle product B C^-1 A D^-1 B^T
-  launch_fill<T>(st, P.v1, T(0), vl);
-  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, P.py, nullptr, nullptr, nullptr);
-  launch_fill<T>(st, P.v2, T(0), vl);
+  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, P.py, nullptr, nullptr, false,
+               s.opwork);
   launch_op<T>(st, F_A | F_DIR, 3, m.N, m.k, P.v1, P.v2, fine_mu(s, P), nullptr, nullptr, P.winv[1],
+               false, s.opwork);
+  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, P.winv[0], false,
                nullptr);
-  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, P.winv[0], nullptr);
   launch_remove_mean<T>(st, m.E, m.np, P.pm, s.red_partial, s.red_out + 2);
   apply_vcycle_K<T>(s, P, 0, P.pm, z);
 }
@@ -550,8 +549,8 @@ void apply_precond(Solver& s, Precond<T>& P, const T* ru, const T* rp, T* zu, T*
   const Mesh& m = s.m;
   const size_t vl = (size_t)3 * m.nn;
   apply_wbfbt<T>(s, P, rp, zp);
-  launch_fill<T>(st, P.v1, T(0), vl);
-  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, zp, nullptr, nullptr, nullptr);
+  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, zp, nullptr, nullptr, false,
+               s.opwork);
   launch_sub<T>(st, vl, ru, P.v1, P.v2);
   apply_vcycle_A<T>(s, P, P.v2, zu);
 }
@@ -592,6 +591,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   WB_REQUIRE(o.cheb_degree >= 1 && o.restart >= 1 && o.max_iter >= 1 && o.rtol > 0, WB_EINVAL,
              "bad solver options");
   WB_REQUIRE(o.a_l >= 1.0 && o.a_r >= 1.0, WB_EINVAL, "boundary amplification must be >= 1");
+  WB_REQUIRE(o.p_schedule == 0 || o.p_schedule == 1, WB_EINVAL, "p_schedule must be 0 or 1");
   WB_REQUIRE(o.precond_prec == WB_FP64 || o.precond_prec == WB_FP32, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
@@ -604,6 +604,14 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.red_partial = ar.alloc<double>(RED_BLOCKS * 128);
   s.red_out = ar.alloc<double>(8);
   const int n3 = (m.k + 1) * (m.k + 1) * (m.k + 1);
+  {
+    size_t wbytes = op_workspace_bytes(3, m.N, m.k, sizeof(double));
+    for (auto& lv : level_schedule(m.N, m.k, o.p_schedule)) {
+      wbytes = std::max(wbytes, op_workspace_bytes(3, lv.first, lv.second, sizeof(double)));
+      wbytes = std::max(wbytes, op_workspace_bytes(1, lv.first, lv.second, sizeof(double)));
+    }
+    s.opwork = ar.raw(wbytes);
+  }
   s.mu_q = ar.alloc<double>((size_t)m.E * n3);
   WB_HIP(hipMemcpyAsync(s.mu_q, mu_q, sizeof(double) * m.E * n3, hipMemcpyDeviceToDevice, st));
 
@@ -678,32 +686,26 @@ namespace {
 void stokes_matvec(Solver& s, const double* x, double* y) {
   const Mesh& m = s.m;
   const size_t vl = (size_t)3 * m.nn;
-  launch_fill<double>(s.st, y, 0.0, vl);
   launch_op<double>(s.st, F_A | F_BT | F_B | F_DIR, 3, m.N, m.k, x, y, s.mu_q, x + vl, y + vl, nullptr,
-                    nullptr);
+                    false, s.opwork);
 }
 }  // namespace
 
-wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep) {
-  const double t0 = now_s();
+// Right-preconditioned flexible GMRES(restart) on a vector of length n with x0 = 0, using the
+// solver's Krylov storage.  Classical Gram-Schmidt with two passes.  On return s.xvec holds x;
+// *iters and *relres the iteration count and the true relative residual.
+template <typename MatVec, typename Prec>
+wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Prec&& precond,
+                      double rtol, int max_iter, int* iters, double* relres_out) {
   hipStream_t st = s.st;
-  const Mesh& m = s.m;
-  const size_t n = s.n_tot, vl = (size_t)3 * m.nn, pl = (size_t)m.E * m.np;
   const int R = s.o.restart;
-  s.learned_used = s.fell_back = 0;
-  // b = [f with zero boundary entries; 0]
-  WB_HIP(hipMemcpyAsync(s.bvec, f, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
-  launch_mask_boundary<double>(st, m.M, 3, s.bvec);
-  launch_fill<double>(st, s.bvec + vl, 0.0, pl);
   launch_fill<double>(st, s.xvec, 0.0, n);
-  const double bnorm = std::sqrt(dot_host(s, n, s.bvec, s.bvec));
+  const double bnorm = std::sqrt(dot_host(s, n, b, b));
   int it = 0;
   double relres = 0.0;
   wb_status status = WB_OK;
-  if (bnorm == 0.0) {
-    relres = 0.0;
-  } else {
-    WB_HIP(hipMemcpyAsync(s.w, s.bvec, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  if (bnorm > 0.0) {
+    WB_HIP(hipMemcpyAsync(s.w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     double beta = bnorm;
     std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), hh(2 * (R + 2) + 1);
     bool done = false;
@@ -716,9 +718,8 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
       for (int j = 0; j < R; ++j) {
         double* vj = s.V + (size_t)j * n;
         double* zj = s.Z + (size_t)j * n;
-        apply_precond_any(s, vj, vj + vl, zj, zj + vl);
-        stokes_matvec(s, zj, s.w);
-        // classical Gram-Schmidt, two passes
+        precond(vj, zj);
+        matvec(zj, s.w);
         double* h1 = s.hbuf;
         double* h2 = s.hbuf + (R + 2);
         launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, h1);
@@ -735,14 +736,14 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
         H[(size_t)(j + 1) * R + j] = nrm;
         if (nrm > 0.0) launch_scal<double>(st, n, 1.0 / nrm, s.w, s.V + (size_t)(j + 1) * n);
         for (int i = 0; i < j; ++i) {
-          const double a = H[(size_t)i * R + j], b = H[(size_t)(i + 1) * R + j];
-          H[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
-          H[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+          const double a = H[(size_t)i * R + j], bb = H[(size_t)(i + 1) * R + j];
+          H[(size_t)i * R + j] = cs[i] * a + sn[i] * bb;
+          H[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * bb;
         }
-        const double a = H[(size_t)j * R + j], b = H[(size_t)(j + 1) * R + j];
-        const double den = std::hypot(a, b);
+        const double a = H[(size_t)j * R + j], bb = H[(size_t)(j + 1) * R + j];
+        const double den = std::hypot(a, bb);
         cs[j] = a / den;
-        sn[j] = b / den;
+        sn[j] = bb / den;
         H[(size_t)j * R + j] = den;
         H[(size_t)(j + 1) * R + j] = 0.0;
         g[j + 1] = -sn[j] * g[j];
@@ -750,9 +751,8 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
         ++it;
         jdone = j + 1;
         if (s.o.verbose) fprintf(stderr, "fgmres %4d  %.3e\n", it, std::fabs(g[j + 1]) / bnorm);
-        if (std::fabs(g[j + 1]) <= s.o.rtol * bnorm || it >= s.o.max_iter || nrm == 0.0) break;
+        if (std::fabs(g[j + 1]) <= rtol * bnorm || it >= max_iter || nrm == 0.0) break;
       }
-      // y = H^-1 g, x += Z y
       std::vector<double> y(jdone);
       for (int i = jdone - 1; i >= 0; --i) {
         double t = g[i];
@@ -762,17 +762,38 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
       WB_HIP(hipMemcpyAsync(s.hbuf, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, st));
       launch_gemv_add(st, n, jdone, s.Z, n, s.hbuf, s.xvec);
       // true residual
-      stokes_matvec(s, s.xvec, s.w);
-      launch_axpby<double>(st, n, 1.0, s.bvec, -1.0, s.w);
+      matvec(s.xvec, s.w);
+      launch_axpby<double>(st, n, 1.0, b, -1.0, s.w);
       beta = std::sqrt(dot_host(s, n, s.w, s.w));
       relres = beta / bnorm;
-      if (relres <= s.o.rtol) done = true;
-      else if (it >= s.o.max_iter) {
+      if (relres <= rtol) done = true;
+      else if (it >= max_iter) {
         status = WB_ENOCONV;
         done = true;
       }
     }
   }
+  *iters = it;
+  *relres_out = relres;
+  return status;
+}
+
+wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep) {
+  const double t0 = now_s();
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  const size_t n = s.n_tot, vl = (size_t)3 * m.nn, pl = (size_t)m.E * m.np;
+  s.learned_used = s.fell_back = 0;
+  // b = [f with zero boundary entries; 0]
+  WB_HIP(hipMemcpyAsync(s.bvec, f, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
+  launch_mask_boundary<double>(st, m.M, 3, s.bvec);
+  launch_fill<double>(st, s.bvec + vl, 0.0, pl);
+  int it = 0;
+  double relres = 0.0;
+  const wb_status status = fgmres_core(
+      s, n, s.bvec, [&](const double* x, double* y) { stokes_matvec(s, x, y); },
+      [&](const double* v, double* z) { apply_precond_any(s, v, v + vl, z, z + vl); }, s.o.rtol,
+      s.o.max_iter, &it, &relres);
   launch_remove_mean<double>(st, m.E, m.np, s.xvec + vl, s.red_partial, s.red_out + 3);
   WB_HIP(hipMemcpyAsync(u, s.xvec, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
   WB_HIP(hipMemcpyAsync(p, s.xvec + vl, sizeof(double) * pl, hipMemcpyDeviceToDevice, st));
@@ -784,6 +805,53 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
     rep->t_solve_s = now_s() - t0;
     rep->fell_back = s.fell_back;
     rep->learned_used = s.learned_used;
+    rep->device_bytes = s.arena.bytes();
+  }
+  return status;
+}
+
+wb_status subsolve(Solver& s, int which, const double* b_in, double* x, wb_report* rep) {
+  const double t0 = now_s();
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  Precond<double>& P = *s.pd;
+  const size_t vl = (size_t)3 * m.nn, pl = (size_t)m.E * m.np;
+  int it = 0;
+  double relres = 0.0;
+  wb_status status;
+  if (which == 0) {
+    // A u = f with one velocity V-cycle as preconditioner
+    WB_HIP(hipMemcpyAsync(s.bvec, b_in, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
+    launch_mask_boundary<double>(st, m.M, 3, s.bvec);
+    status = fgmres_core(
+        s, vl, s.bvec,
+        [&](const double* xx, double* yy) {
+          launch_op<double>(st, F_A | F_DIR, 3, m.N, m.k, xx, yy, s.mu_q, nullptr, nullptr, nullptr,
+                            false, s.opwork);
+        },
+        [&](const double* v, double* z) { apply_vcycle_A<double>(s, P, v, z); }, s.o.rtol,
+        s.o.max_iter, &it, &relres);
+    WB_HIP(hipMemcpyAsync(x, s.xvec, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
+  } else {
+    // K_w p = g (w left for which == 1, right for which == 2) with one K_w V-cycle; g and p mean-free
+    const int side = which - 1;
+    WB_HIP(hipMemcpyAsync(s.bvec, b_in, sizeof(double) * pl, hipMemcpyDeviceToDevice, st));
+    launch_remove_mean<double>(st, m.E, m.np, s.bvec, s.red_partial, s.red_out + 4);
+    status = fgmres_core(
+        s, pl, s.bvec, [&](const double* xx, double* yy) { apply_K<double>(s, P, side, xx, yy); },
+        [&](const double* v, double* z) { apply_vcycle_K<double>(s, P, side, v, z); }, s.o.rtol,
+        s.o.max_iter, &it, &relres);
+    launch_remove_mean<double>(st, m.E, m.np, s.xvec, s.red_partial, s.red_out + 4);
+    WB_HIP(hipMemcpyAsync(x, s.xvec, sizeof(double) * pl, hipMemcpyDeviceToDevice, st));
+  }
+  WB_HIP(hipStreamSynchronize(st));
+  if (rep) {
+    rep->iters = it;
+    rep->rel_res = relres;
+    rep->t_setup_s = s.t_setup;
+    rep->t_solve_s = now_s() - t0;
+    rep->fell_back = 0;
+    rep->learned_used = 0;
     rep->device_bytes = s.arena.bytes();
   }
   return status;

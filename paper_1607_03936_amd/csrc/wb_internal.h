@@ -74,6 +74,7 @@ struct Mesh {
 
 struct wb_mesh {
   wb::Mesh m;
+  mutable void* work = nullptr;  // face-array workspace of standalone operator applies
 };
 
 struct wb_visc {

@@ -29,7 +29,8 @@ class wb_opts(ctypes.Structure):
                 ("cheb_degree", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("precond_prec", ctypes.c_int),
-                ("use_learned", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("use_learned", ctypes.c_int), ("p_schedule", ctypes.c_int),
+                ("verbose", ctypes.c_int)]
 
 
 class wb_report(ctypes.Structure):
@@ -69,6 +70,7 @@ SIGNATURES = {
     "wb_apply_vcycle_K": (I, [VP, I, VP, VP, VP]),
     "wb_apply_precond": (I, [VP, VP, VP, VP, VP, VP]),
     "wb_solve": (I, [VP, VP, VP, VP, ctypes.POINTER(wb_report), VP]),
+    "wb_subsolve": (I, [VP, I, VP, VP, ctypes.POINTER(wb_report), VP]),
     "wb_solver_query": (I, [VP, I, I, VP, VP]),
     "wb_solver_levels": (I, [VP, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                              ctypes.POINTER(D)]),
@@ -295,6 +297,16 @@ class Solver:
         rep = wb_report()
         code = lib().wb_solve(self.h, _ptr(f, f64, m.u_len), _ptr(u, f64, m.u_len),
                               _ptr(p, f64, m.p_len), ctypes.byref(rep), _stream(stream))
+        if not (allow_noconv and code == WB_ENOCONV):
+            _check(code)
+        return rep
+
+    def subsolve(self, which, b, x, stream=None, allow_noconv=False):
+        """GMRES on A (which=0) or K_l / K_r (1 / 2) with one V-cycle as preconditioner."""
+        import torch
+        rep = wb_report()
+        code = lib().wb_subsolve(self.h, which, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                                 ctypes.byref(rep), _stream(stream))
         if not (allow_noconv and code == WB_ENOCONV):
             _check(code)
         return rep
