@@ -140,22 +140,31 @@ struct WaveMap {
 
 // 1D tables are centro-symmetric: B(n-1-q, n-1-l) = B(q, l) and Dh(n-1-q, n-1-m) = -Dh(q, m)
 // (symmetric Gauss points, symmetric GLL nodes); Dh vanishes at the middle of an odd rule.
-// Referencing only the first half of each table keeps the distinct constants (scalar
-// registers) at about half; the indices are compile-time after unrolling.
+// The element kernels read the compile-time tables CT<n> with compile-time indices (after
+// unrolling), so every entry is a literal; referencing only the first half of each table keeps
+// the distinct constants at about half and lets sign modifiers supply the rest.
 template <int n, typename T>
-__device__ __forceinline__ T Bm(const KT<n, T>& tb, int q, int l) {
+__device__ __forceinline__ T Bm(int q, int l) {
   constexpr int H = n / 2;
-  if (q < H) return tb.B[q * n + l];
-  if (q >= n - H) return tb.B[(n - 1 - q) * n + (n - 1 - l)];
-  return tb.B[q * n + (l <= H ? l : n - 1 - l)];           // middle row of an odd rule
+  if (q < H) return (T)CT<n>::t.B[q * n + l];
+  if (q >= n - H) return (T)CT<n>::t.B[(n - 1 - q) * n + (n - 1 - l)];
+  return (T)CT<n>::t.B[q * n + (l <= H ? l : n - 1 - l)];  // middle row of an odd rule
 }
 template <int n, typename T>
-__device__ __forceinline__ T Dm(const KT<n, T>& tb, int q, int m) {
+__device__ __forceinline__ T Dm(int q, int m) {
   constexpr int H = n / 2;
-  if (q < H) return tb.Dh[q * n + m];
-  if (q >= n - H) return -tb.Dh[(n - 1 - q) * n + (n - 1 - m)];
+  if (q < H) return (T)CT<n>::t.Dh[q * n + m];
+  if (q >= n - H) return -(T)CT<n>::t.Dh[(n - 1 - q) * n + (n - 1 - m)];
   if (m == H) return T(0);
-  return m < H ? tb.Dh[q * n + m] : -tb.Dh[q * n + (n - 1 - m)];
+  return m < H ? (T)CT<n>::t.Dh[q * n + m] : -(T)CT<n>::t.Dh[q * n + (n - 1 - m)];
+}
+template <int n, typename T>
+__device__ __forceinline__ T Wg(int q) {
+  return (T)CT<n>::t.wg[q < n / 2 ? q : n - 1 - q];
+}
+template <int n, typename T>
+__device__ __forceinline__ T Lg(int a, int q) {
+  return (T)CT<n>::t.L[a * n + q];
 }
 
 // LDS layout of an element's scratch: value (x, y, z) at x + SY y + SZ z, slots SL apart.  The
@@ -191,28 +200,53 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
   const bool bij = (gi == 0) || (gi == M - 1) || (gj == 0) || (gj == M - 1);
   T S[NC][3][n];  // z-line role: gradients, then stresses, at (a, b, q)
   T bq[n];
+  T cq[n];        // coefficient at (a, b, q)
 
   if constexpr ((F & (F_A | F_B)) != 0) {
+    // All global loads of the element are issued up front from in-bounds addresses (index 0
+    // for idle lanes); masked values are selected away afterwards.
     int gidx[n];
-    T sc[n];
+    bool live[n];
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       const int gl = ez * k + l;
-      gidx[l] = gi + M * (gj + M * gl);
       const bool bnd = (F & F_DIR) && (bij || gl == 0 || gl == M - 1);
-      sc[l] = (valid && !bnd) ? ((sin_ != nullptr) ? sin_[gidx[l]] : T(1)) : T(0);
+      live[l] = valid && !bnd;
+      gidx[l] = valid ? gi + M * (gj + M * gl) : 0;
     }
+    T uz[NC][n];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int l = 0; l < n; ++l) uz[c][l] = u[(size_t)c * nn + gidx[l]];
+    if constexpr ((F & F_A) != 0) {
+      const size_t eb = (size_t)(valid ? e : 0) * N3 + b * n + a;
+#pragma unroll
+      for (int q = 0; q < n; ++q) cq[q] = coef[eb + q * NN];
+    }
+    if (sin_ != nullptr) {
+#pragma unroll
+      for (int l = 0; l < n; ++l) {
+        const T sl = sin_[gidx[l]];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uz[c][l] *= sl;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int l = 0; l < n; ++l) uz[c][l] = live[l] ? uz[c][l] : T(0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T v[n], w[n];
       // z: interpolate the node column to the Gauss points
 #pragma unroll
-      for (int l = 0; l < n; ++l) v[l] = sc[l] != T(0) ? u[(size_t)c * nn + gidx[l]] * sc[l] : T(0);
+      for (int l = 0; l < n; ++l) v[l] = uz[c][l];
 #pragma unroll
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int l = 0; l < n; ++l) acc += Bm(tb, q, l) * v[l];
+        for (int l = 0; l < n; ++l) acc += Bm<n, T>(q, l) * v[l];
         s[a + SY * b + SZ * q] = acc;
       }
       wave_sync();
@@ -223,7 +257,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm(tb, q, m) * v[m];
+        for (int m = 0; m < n; ++m) acc += Bm<n, T>(q, m) * v[m];
         s[a + SY * q + SZ * b] = acc;
       }
       wave_sync();
@@ -234,14 +268,14 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm(tb, q, m) * v[m];
+        for (int m = 0; m < n; ++m) acc += Bm<n, T>(q, m) * v[m];
         w[q] = acc;
       }
 #pragma unroll
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm(tb, q, m) * w[m];
+        for (int m = 0; m < n; ++m) acc += Dm<n, T>(q, m) * w[m];
         s[q + SY * a + SZ * b] = w[q];
         s2[q + SY * a + SZ * b] = acc;
       }
@@ -253,7 +287,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm(tb, q, m) * v[m];
+        for (int m = 0; m < n; ++m) acc += Dm<n, T>(q, m) * v[m];
         w[q] = acc;
       }
 #pragma unroll
@@ -262,7 +296,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm(tb, q, m) * v[m];
+        for (int m = 0; m < n; ++m) acc += Dm<n, T>(q, m) * v[m];
         S[c][2][q] = acc;
       }
       wave_sync();
@@ -277,14 +311,14 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       wave_sync();
     }
     // pointwise at (a, b, q)
-    const T wab = tb.w[a] * tb.w[b];
+    const T wab = Wg<n, T>(a) * Wg<n, T>(b);
 #pragma unroll
     for (int q = 0; q < n; ++q) {
-      const T w3 = wab * tb.w[q];
+      const T w3 = wab * Wg<n, T>(q);
       if constexpr (NC == 3) {
         if constexpr ((F & F_B) != 0) bq[q] = -hh * hh * w3 * (S[0][0][q] + S[1][1][q] + S[2][2][q]);
         if constexpr ((F & F_A) != 0) {
-          const T cw = valid ? coef[(size_t)e * N3 + q * NN + b * n + a] * w3 * hh : T(0);
+          const T cw = valid ? cq[q] * w3 * hh : T(0);
           const T s01 = cw * (S[0][1][q] + S[1][0][q]);
           const T s02 = cw * (S[0][2][q] + S[2][0][q]);
           const T s12 = cw * (S[1][2][q] + S[2][1][q]);
@@ -301,7 +335,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
             for (int d = 0; d < 3; ++d) S[c][d][q] = T(0);
         }
       } else {
-        const T cw = valid ? coef[(size_t)e * N3 + q * NN + b * n + a] * w3 * hh : T(0);
+        const T cw = valid ? cq[q] * w3 * hh : T(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) S[0][d][q] *= cw;
       }
@@ -321,18 +355,18 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
     for (int c = 0; c < n - 1; ++c) {
       T acc = T(0);
 #pragma unroll
-      for (int q = 0; q < n; ++q) acc += tb.L[c * n + q] * bq[q];
+      for (int q = 0; q < n; ++q) acc += Lg<n, T>(c, q) * bq[q];
       s[a + SY * b + SZ * c] = acc;
     }
     wave_sync();
     if (valid && r < NP) {
-      const int ma = tb.ma[r], mb = tb.mb[r], mc = tb.mc[r];
+      const int ma = CT<n>::t.ma[r], mb = CT<n>::t.mb[r], mc = CT<n>::t.mc[r];
       T acc = T(0);
 #pragma unroll
       for (int jj = 0; jj < n; ++jj)
 #pragma unroll
         for (int ii = 0; ii < n; ++ii)
-          acc += tb.L[ma * n + ii] * tb.L[mb * n + jj] * s[ii + SY * jj + SZ * mc];
+          acc += Lg<n, T>(ma, ii) * Lg<n, T>(mb, jj) * s[ii + SY * jj + SZ * mc];
       pout[(size_t)e * NP + r] = acc;
     }
     wave_sync();
@@ -342,19 +376,19 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
     T La[n - 1], Lb[n - 1];
 #pragma unroll
     for (int m = 0; m < n - 1; ++m) {
-      La[m] = tb.L[m * n + a];
-      Lb[m] = tb.L[m * n + b];
+      La[m] = Lg<n, T>(m, a);
+      Lb[m] = Lg<n, T>(m, b);
     }
-    const T wab = tb.w[a] * tb.w[b];
+    const T wab = Wg<n, T>(a) * Wg<n, T>(b);
 #pragma unroll
     for (int q = 0; q < n; ++q) {
       T pq = T(0);
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
         const T pmv = valid ? pin[(size_t)e * NP + m] : T(0);
-        pq += pmv * La[tb.ma[m]] * Lb[tb.mb[m]] * tb.L[tb.mc[m] * n + q];
+        pq += pmv * La[CT<n>::t.ma[m]] * Lb[CT<n>::t.mb[m]] * Lg<n, T>(CT<n>::t.mc[m], q);
       }
-      const T vv = -hh * hh * wab * tb.w[q] * pq;
+      const T vv = -hh * hh * wab * Wg<n, T>(q) * pq;
       S[0][0][q] += vv;
       S[1][1][q] += vv;
       S[2][2][q] += vv;
@@ -369,7 +403,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm(tb, m, q) * S[c][2][m];
+        for (int m = 0; m < n; ++m) acc += Dm<n, T>(m, q) * S[c][2][m];
         V[q] = acc;
         s[a + SY * b + SZ * q] = S[c][0][q];
         s2[a + SY * b + SZ * q] = S[c][1][q];
@@ -382,7 +416,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm(tb, m, q) * v[m];
+        for (int m = 0; m < n; ++m) acc += Dm<n, T>(m, q) * v[m];
         s[q + SY * a + SZ * b] = acc;
       }
 #pragma unroll
@@ -391,7 +425,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm(tb, m, q) * v[m];
+        for (int m = 0; m < n; ++m) acc += Dm<n, T>(m, q) * v[m];
         s2[a + SY * q + SZ * b] = acc;
       }
       wave_sync();
@@ -403,7 +437,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int l = 0; l < n; ++l) {
         T acc = T(0);
 #pragma unroll
-        for (int q = 0; q < n; ++q) acc += Bm(tb, q, l) * V[q];
+        for (int q = 0; q < n; ++q) acc += Bm<n, T>(q, l) * V[q];
         s[a + SY * b + SZ * l] = acc;
       }
       wave_sync();
@@ -414,7 +448,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm(tb, m, q) * v[m];
+        for (int m = 0; m < n; ++m) acc += Bm<n, T>(m, q) * v[m];
         s[a + SY * q + SZ * b] = acc;
       }
       wave_sync();
@@ -425,7 +459,7 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       for (int q = 0; q < n; ++q) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm(tb, m, q) * v[m];
+        for (int m = 0; m < n; ++m) acc += Bm<n, T>(m, q) * v[m];
         sink(c, q, a, b, acc);
       }
       wave_sync();

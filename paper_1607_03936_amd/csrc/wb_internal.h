@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/wbfbt.h"
+#include "rules.h"
 
 namespace wb {
 
@@ -43,22 +44,7 @@ double legendre(int a, double x);
 // Modes (a,b,c) with a+b+c <= k-1, c slowest, a fastest.
 int modes(int k, int* ma, int* mb, int* mc);
 
-constexpr int NMAX = 5;   // n = k+1 <= 5
-constexpr int NPMAX = 20; // modes for k = 4
-
-// All 1D tables of one order k (n = k+1), double precision; kernels receive a
-// per-order copy by value.
-struct Tables {
-  int n, k, np;
-  double xg[NMAX], wg[NMAX];           // Gauss points / weights
-  double xl[NMAX], wl[NMAX];           // GLL nodes / weights
-  double B[NMAX * NMAX];               // B[q*n+a] = l_a(xg_q), GLL Lagrange at Gauss points
-  double D1[NMAX * NMAX];              // D1[q*n+a] = l_a'(xg_q)
-  double Dh[NMAX * NMAX];              // Dh[q*n+p] = derivative at xg_q of Gauss-Lagrange l^G_p
-  double L[NMAX * NMAX];               // L[a*n+q] = P_a(xg_q)
-  double J[NMAX * NMAX];               // J[a*n+i] = sum_q wg_q P_a(xg_q) B[q,i] / (2/(2a+1))
-  int ma[NPMAX], mb[NPMAX], mc[NPMAX]; // pressure modes
-};
+// All 1D tables of one order k (n = k+1) and the compile-time copy CT<n>: see rules.h.
 const Tables& tables(int k);
 
 // --------------------------------------------------------------- handles
