@@ -5,9 +5,12 @@ One step = the whole hot path on the seeded multi-sinker workload: viscosity at
 the quadrature points and nodes, body force, solver setup (multigrid hierarchy,
 w-BFBT weights and diagonals, Chebyshev bounds, coarsest factorizations) and the
 FP64 FGMRES solve to relative residual 1e-6.  `value` = (u-DOF + p-DOF) per
-second of step time (GDoF/s, whole job).  Also reported: the A(mu)-apply rate
-and roofline of the dominant kernel (HIP events inside the timed steps), the
-mixed-precision form, and the CPU oracle on a bounded sample.
+second of step time (GDoF/s, whole job); the FGMRES preconditioner applies are
+replayed from a HIP graph.  Also reported: the kernel classes of one eagerly
+launched step, the A(mu)-apply rate and roofline (100 applies bracketed by HIP
+events on their stream, at the workload and at 64^3 Q3, where the working set
+exceeds the Infinity Cache), the mixed-precision form, and the CPU oracle on a
+bounded sample.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
 """
@@ -63,6 +66,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-big", action="store_true", help="skip the 64^3 Q3 A-apply measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -85,11 +89,11 @@ def main():
     u = torch.empty(mesh.u_len, dtype=torch.float64, device="cuda")
     p = torch.empty(mesh.p_len, dtype=torch.float64, device="cuda")
 
-    def step(prec=wb.WB_FP64):
+    def step(prec=wb.WB_FP64, use_graph=1):
         t0 = time.perf_counter()
         v = wb.Viscosity.sinker(mesh, centers, w.delta, w.omega, w.mu_min, w.mu_max)
         wb.wb_rhs_sinker(mesh, centers, w.delta, w.omega, w.beta, f)
-        s = wb.Solver(mesh, v, a_l=w.a_l, a_r=w.a_r, precond_prec=prec)
+        s = wb.Solver(mesh, v, a_l=w.a_l, a_r=w.a_r, precond_prec=prec, use_graph=use_graph)
         t1 = time.perf_counter()
         rep = s.solve(f, u, p, allow_noconv=True)
         torch.cuda.synchronize()
@@ -102,8 +106,6 @@ def main():
         rep, ts, tv = step()
         log(f"[bench] warmup {i}: setup {ts:.3f}s solve {tv:.3f}s iters {rep.iters} res {rep.rel_res:.2e}")
     torch.cuda.synchronize()
-    wb.wb_profile_enable(True)
-    wb.wb_profile_summary(reset=True)
     setups, solves, iters, res = [], [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -115,43 +117,35 @@ def main():
         log(f"[bench] step {i}: setup {ts:.3f}s solve {tv:.3f}s iters {rep.iters} res {rep.rel_res:.2e}")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
-    wb.wb_profile_enable(False)
-    prof = wb.wb_profile_summary(reset=True)
     ms_per_step = 1e3 * t_total / args.steps
     u64, p64 = u.clone(), p.clone()
 
-    # dominant operator kernel class in the timed steps (HIP events on its stream)
-    dom_key, (dom_n, dom_ms) = max(prof.items(), key=lambda kv: kv[1][1])
-    dom_avg_ms = dom_ms / dom_n
-    dom_bytes = op_bytes(dom_key, w.N, w.k)
-    achieved = dom_bytes / (dom_avg_ms * 1e-3) / 1e9
-    op_total_ms = sum(v[1] for v in prof.values()) / args.steps
-
-    # A(mu)-apply rate at the fine level: 100 back-to-back accumulate applies, event-timed
-    v = wb.Viscosity.sinker(mesh, centers, w.delta, w.omega, w.mu_min, w.mu_max)
-    x = torch.rand(mesh.u_len, dtype=torch.float64, device="cuda")
-    y = torch.zeros(mesh.u_len, dtype=torch.float64, device="cuda")
-    for _ in range(10):
-        wb.wb_apply_A_add(mesh, v, x, y)
-    torch.cuda.synchronize()
+    # kernel classes of one step, from an untimed step with every launch issued eagerly
+    # (launches replayed from the graph carry no per-launch events)
     wb.wb_profile_enable(True)
     wb.wb_profile_summary(reset=True)
-    for _ in range(100):
-        wb.wb_apply_A_add(mesh, v, x, y)
+    rep, ts, tv = step(use_graph=0)
     torch.cuda.synchronize()
     wb.wb_profile_enable(False)
-    aprof = wb.wb_profile_summary(reset=True)
-    a_key, (a_n, a_ms) = next(iter(aprof.items()))
-    a_avg = a_ms / a_n
-    a_bytes = op_bytes(a_key, w.N, w.k)
-    a_apply = {"kernel": a_key, "launches": a_n, "avg_ms": round(a_avg, 5),
-               "gdofs": round(mesh.u_len / (a_avg * 1e-3) / 1e9, 3),
-               "algorithmic_GBs": round(a_bytes / (a_avg * 1e-3) / 1e9, 1),
-               "hbm_frac": round(a_bytes / (a_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-               "bytes_per_launch": a_bytes,
-               "cache_note": ("working set %.0f MB %s the 256 MB Infinity Cache"
-                              % (a_bytes / 1e6, "fits in" if a_bytes < 256e6 else "exceeds"))}
-    del v
+    prof = wb.wb_profile_summary(reset=True)
+    log(f"[bench] eager profiled step: setup {ts:.3f}s solve {tv:.3f}s iters {rep.iters}")
+    step_total = sum(v[1] for v in prof.values())
+    step_kernels = [{"kernel": k, "launches": n, "ms": round(ms, 3),
+                     "share": round(ms / step_total, 4)}
+                    for k, (n, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])[:6]]
+
+    # the A(mu) apply at the finest level: 100 back-to-back accumulating applies, each
+    # bracketed by HIP events on the stream it is launched on
+    a_apply = measure_a_apply(wb, torch, mesh, w, centers)
+    log(f"[bench] A apply {w.name}: {a_apply['avg_ms'] * 1e3:.1f} us, {a_apply['gdofs']} GDoF/s")
+    a_big = None
+    if not args.no_big and w.name != "c5":
+        wbig = WORKLOADS["c5"]
+        mbig = wb.Mesh(wbig.N, wbig.k)
+        a_big = measure_a_apply(wb, torch, mbig, wbig, wbig.centers())
+        log(f"[bench] A apply c5: {a_big['avg_ms'] * 1e3:.1f} us, {a_big['gdofs']} GDoF/s")
+        del mbig
+        torch.cuda.empty_cache()
 
     forms = {"fp64": {"setup_s": round(float(np.median(setups)), 4),
                       "solve_s": round(float(np.median(solves)), 4),
@@ -184,14 +178,72 @@ def main():
                    "step": "viscosity + body force + solver setup + FP64 FGMRES solve"},
         "solve": forms,
         "a_apply": a_apply,
-        "op_kernels_ms_per_step": round(op_total_ms, 3),
-        "roofline": {"kernel": dom_key, "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "launches": dom_n, "avg_ms": round(dom_avg_ms, 5),
-                     "bytes_per_launch": dom_bytes},
+        "a_apply_64cubed_q3": a_big,
+        "step_kernels_eager": step_kernels,
+        "roofline": {"kernel": a_apply["kernel"], "bound": "hbm", "achieved": a_apply["algorithmic_GBs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(a_apply["algorithmic_GBs"] / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_for(a_apply["kernel"]), "launches": a_apply["launches"],
+                     "avg_ms": a_apply["avg_ms"], "bytes_per_launch": a_apply["bytes_per_launch"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_a_apply(wb, torch, mesh, w, centers, reps=100):
+    v = wb.Viscosity.sinker(mesh, centers, w.delta, w.omega, w.mu_min, w.mu_max)
+    x = torch.rand(mesh.u_len, dtype=torch.float64, device="cuda")
+    y = torch.zeros(mesh.u_len, dtype=torch.float64, device="cuda")
+    for _ in range(10):
+        wb.wb_apply_A_add(mesh, v, x, y)
+    torch.cuda.synchronize()
+    wb.wb_profile_enable(True)
+    wb.wb_profile_summary(reset=True)
+    for _ in range(reps):
+        wb.wb_apply_A_add(mesh, v, x, y)
+    torch.cuda.synchronize()
+    wb.wb_profile_enable(False)
+    aprof = wb.wb_profile_summary(reset=True)
+    # the brick kernel itself (the face-sum pass is its own, smaller class)
+    a_key, (a_n, a_ms) = next((k, x) for k, x in aprof.items() if k.startswith("op "))
+    a_avg = a_ms / a_n
+    a_bytes = op_bytes(a_key, mesh.N, mesh.k)
+    faces = [x for k, x in aprof.items() if k.startswith("op-faces")]
+    f_avg = faces[0][1] / faces[0][0] if faces else 0.0
+    del v, x, y
+    return {"kernel": a_key, "launches": a_n, "avg_ms": round(a_avg, 5),
+            "face_pass_avg_ms": round(f_avg, 5),
+            "gdofs": round(mesh.u_len / (a_avg * 1e-3) / 1e9, 3),
+            "gdofs_incl_face_pass": round(mesh.u_len / ((a_avg + f_avg) * 1e-3) / 1e9, 3),
+            "algorithmic_GBs": round(a_bytes / (a_avg * 1e-3) / 1e9, 1),
+            "hbm_frac": round(a_bytes / (a_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": a_bytes,
+            "cache_note": ("working set %.0f MB %s the 256 MB Infinity Cache"
+                           % (a_bytes / 1e6, "fits in" if a_bytes < 256e6 else "exceeds"))}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "rules.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1607_03936_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch of the kernel class from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or None when no summary
+    covers this kernel or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(kernel_key)
+    return None if ent is None else ent["bytes_per_launch"]
 
 
 def cpu_baseline(w, Ns):

@@ -75,6 +75,9 @@ typedef struct {
   int p_schedule;         /* order coarsening: 0 halves k (4->2->1, 3->1, 2->1),
                              1 lowers it by one (4->3->2->1, 3->2->1)              */
   int verbose;            /* 1: print the residual history to stderr              */
+  int use_graph;          /* 1: wb_solve replays the preconditioner apply from a
+                             HIP graph captured at its first iteration (default);
+                             0: every launch is issued from the host             */
 } wb_opts;
 
 typedef struct {

@@ -94,6 +94,7 @@ void wb_opts_default(wb_opts* o) {
   o->precond_prec = WB_FP64;
   o->use_learned = 0;
   o->verbose = 0;
+  o->use_graph = 1;
 }
 
 const char* wb_last_error(void) { return g_err.c_str(); }

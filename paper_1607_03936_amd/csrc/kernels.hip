@@ -722,6 +722,8 @@ struct ProfScope {
   std::string key;
   ProfScope(hipStream_t s, std::string k) : st(s), key(std::move(k)) {
     if (!prof::on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> g(prof::mu);
     a = prof::get_event();
     b = prof::get_event();
@@ -1190,16 +1192,38 @@ __global__ void k_mode0_sub(int E, int np, T* __restrict__ p, const double* __re
   if (e < E) p[(size_t)e * np] -= (T)(*sum / E);
 }
 
+// h[v] partials for a group of MDOT_VG basis vectors: block (bx, g) covers the rows
+// bx*256 + t, stepping gridDim.x*256, for vectors g*MDOT_VG ...; every row of w is read once per
+// group and MDOT_VG independent streams are in flight per thread.
+constexpr int MDOT_VG = 8;
 __global__ void __launch_bounds__(256) k_mdot_partial(size_t n, int nv, const double* __restrict__ V,
                                                       size_t ld, const double* __restrict__ w,
                                                       double* partial) {
-  for (int v = 0; v < nv; ++v) {
-    const double* Vv = V + (size_t)v * ld;
-    double s = 0.0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-      s += Vv[i] * w[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) partial[(size_t)v * gridDim.x + blockIdx.x] = s;
+  __shared__ double red[4][MDOT_VG];
+  const int v0 = blockIdx.y * MDOT_VG;
+  const int cnt = min(MDOT_VG, nv - v0);
+  double acc[MDOT_VG];
+#pragma unroll
+  for (int j = 0; j < MDOT_VG; ++j) acc[j] = 0.0;
+  const double* Vb = V + (size_t)v0 * ld;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < MDOT_VG; ++j)
+      if (j < cnt) acc[j] += Vb[(size_t)j * ld + i] * wi;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < MDOT_VG; ++j) {
+    double v = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wid][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    const int j = threadIdx.x;
+    partial[(size_t)(v0 + j) * gridDim.x + blockIdx.x] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
   }
 }
 
@@ -1471,8 +1495,10 @@ template void launch_cast<double, double>(hipStream_t, size_t, const double*, do
 
 void launch_mdot(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* w,
                  double* partial, double* h) {
-  int nb = (int)std::min<size_t>(256, grid_for(n, 256));
-  hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(256), 0, st, n, nv, V, ld, w, partial);
+  // nb <= 256 row blocks (the partial buffer holds 256 per vector), about 4 rows per thread
+  const int nb = (int)std::min<size_t>(256, std::max<size_t>(1, grid_for(n, 1024)));
+  const int ng = (nv + MDOT_VG - 1) / MDOT_VG;
+  hipLaunchKernelGGL(k_mdot_partial, dim3(nb, ng), dim3(256), 0, st, n, nv, V, ld, w, partial);
   hipLaunchKernelGGL(k_rows_sum, dim3(nv), dim3(256), 0, st, nb, partial, h);
 }
 void launch_gemv_sub(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* h,

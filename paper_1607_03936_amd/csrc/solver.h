@@ -84,6 +84,10 @@ struct Solver {
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hbuf = nullptr, *mpartial = nullptr;
   double *bvec = nullptr, *xvec = nullptr;
   double t_setup = 0.0;
+  // preconditioner apply captured as a HIP graph (on cap_st, into the staging vectors gin/gout)
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t pgraph = nullptr;
+  double *gin = nullptr, *gout = nullptr;
   // learned correction (optional)
   struct Learned* learned = nullptr;
   int learned_used = 0, fell_back = 0;

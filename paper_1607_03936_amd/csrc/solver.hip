@@ -583,7 +583,10 @@ void apply_precond_any(Solver& s, const double* ru, const double* rp, double* zu
 }
 
 // ------------------------------------------------------------------ setup
-Solver::~Solver() {}
+Solver::~Solver() {
+  if (pgraph) (void)hipGraphExecDestroy(pgraph);
+  if (cap_st) (void)hipStreamDestroy(cap_st);
+}
 
 Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes, const wb_opts& o,
                       hipStream_t st) {
@@ -778,6 +781,45 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
   return status;
 }
 
+// The preconditioner apply of FGMRES replayed from a HIP graph.  Its launch sequence (several
+// hundred small kernels for the V-cycles) depends only on the solver, so it is captured once,
+// on a solver-owned stream and between fixed staging vectors, and replayed per iteration on the
+// solver's stream: the input is copied into gin, the graph runs, the result is copied out of gout.
+void precond_graph(Solver& s, const double* v, double* z) {
+  const size_t n = s.n_tot, vl = (size_t)3 * s.m.nn;
+  hipStream_t st = s.st;
+  if (!s.pgraph) {
+    if (!s.gin) {
+      s.gin = s.arena.alloc<double>(n);
+      s.gout = s.arena.alloc<double>(n);
+    }
+    if (!s.cap_st) WB_HIP(hipStreamCreateWithFlags(&s.cap_st, hipStreamNonBlocking));
+    WB_HIP(hipStreamSynchronize(st));
+    hipGraph_t g = nullptr;
+    WB_HIP(hipStreamBeginCapture(s.cap_st, hipStreamCaptureModeRelaxed));
+    s.st = s.cap_st;
+    try {
+      apply_precond_any(s, s.gin, s.gin + vl, s.gout, s.gout + vl);
+    } catch (...) {
+      s.st = st;
+      (void)hipStreamEndCapture(s.cap_st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    s.st = st;
+    WB_HIP(hipStreamEndCapture(s.cap_st, &g));
+    const hipError_t e = hipGraphInstantiate(&s.pgraph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      s.pgraph = nullptr;
+      throw Error{WB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    }
+  }
+  WB_HIP(hipMemcpyAsync(s.gin, v, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  WB_HIP(hipGraphLaunch(s.pgraph, st));
+  WB_HIP(hipMemcpyAsync(z, s.gout, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+}
+
 wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep) {
   const double t0 = now_s();
   hipStream_t st = s.st;
@@ -792,7 +834,11 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
   double relres = 0.0;
   const wb_status status = fgmres_core(
       s, n, s.bvec, [&](const double* x, double* y) { stokes_matvec(s, x, y); },
-      [&](const double* v, double* z) { apply_precond_any(s, v, v + vl, z, z + vl); }, s.o.rtol,
+      [&](const double* v, double* z) {
+        if (s.o.use_graph) precond_graph(s, v, z);
+        else apply_precond_any(s, v, v + vl, z, z + vl);
+      },
+      s.o.rtol,
       s.o.max_iter, &it, &relres);
   launch_remove_mean<double>(st, m.E, m.np, s.xvec + vl, s.red_partial, s.red_out + 3);
   WB_HIP(hipMemcpyAsync(u, s.xvec, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));

@@ -30,7 +30,7 @@ class wb_opts(ctypes.Structure):
                 ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("precond_prec", ctypes.c_int),
                 ("use_learned", ctypes.c_int), ("p_schedule", ctypes.c_int),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class wb_report(ctypes.Structure):

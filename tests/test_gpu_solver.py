@@ -160,3 +160,30 @@ def test_mixed_precision_preconditioner_reaches_tolerance():
     assert r32.iters <= r64.iters + 3
     du = np.linalg.norm(host(u32) - host(u64)) / np.linalg.norm(host(u64))
     assert du < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replayed_preconditioner_matches_eager(prec):
+    """FGMRES replays the captured preconditioner graph once per iteration, with eager kernels
+    and host synchronizations between replays; three solves in a row on one solver must match
+    the eager solve (the LDS-window sums may round in a different order, hence a tolerance)."""
+    wb = _wb()
+    w, st, P, m, v, s = _pair("n8k2")
+    om = st.mesh
+    pp = wb.WB_FP64 if prec == "fp64" else wb.WB_FP32
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    eager = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, precond_prec=pp, use_graph=0)
+    ue = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    pe = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    re = eager.solve(f, ue, pe)
+    graph = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, precond_prec=pp, use_graph=1)
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    for _ in range(3):
+        ug = torch.full_like(ue, float("nan"))
+        pg = torch.full_like(pe, float("nan"))
+        rg = graph.solve(f, ug, pg)
+        assert abs(rg.iters - re.iters) <= 1, (rg.iters, re.iters)
+        assert rg.rel_res <= 1e-6
+        assert _rel(host(ug), host(ue)) < tol
+        assert _rel(host(pg), host(pe)) < tol
