@@ -53,7 +53,12 @@ typedef enum {
   WB_EUNSUPPORTED = 6   /* order or option not built                          */
 } wb_status;
 
-typedef enum { WB_FP64 = 0, WB_FP32 = 1, WB_BF16 = 2 } wb_prec;
+/* Arithmetic of the preconditioner (and of wb_apply_A_lowp).  WB_BF16: FP32 data, every 1D
+ * tensor contraction of the element operators on the BF16 matrix cores with FP32 accumulation,
+ * table and line each split into BF16 high and low parts (three products, about 2^-16 relative
+ * error per contraction).  WB_BF16X1: the same with a single product of BF16-rounded operands
+ * (about 2^-8 per contraction). */
+typedef enum { WB_FP64 = 0, WB_FP32 = 1, WB_BF16 = 2, WB_BF16X1 = 3 } wb_prec;
 
 typedef struct wb_mesh wb_mesh;
 typedef struct wb_visc wb_visc;
@@ -69,8 +74,8 @@ typedef struct {
   int restart;            /* FGMRES restart length (100)                           */
   int max_iter;           /* FGMRES iteration cap (1000)                           */
   double rtol;            /* ||b - K x|| <= rtol ||b|| (1e-6)                      */
-  int precond_prec;       /* wb_prec of the preconditioner: WB_FP64, WB_FP32 or
-                             WB_BF16 (FP32 with BF16 MFMA contractions)            */
+  int precond_prec;       /* wb_prec of the preconditioner: WB_FP64, WB_FP32,
+                             WB_BF16 or WB_BF16X1 (FP32 with BF16 MFMA contractions) */
   int use_learned;        /* 1: learned coarse correction in the velocity V-cycle  */
   int p_schedule;         /* order coarsening: 0 halves k (4->2->1, 3->1, 2->1),
                              1 lowers it by one (4->3->2->1, 3->2->1)              */
@@ -136,8 +141,8 @@ WB_API wb_status wb_apply_A_add(const wb_mesh* m, const wb_visc* v, const double
 /* Fused Stokes operator of eq. (2): yu = A u + B^T p, yp = B u (one kernel). */
 WB_API wb_status wb_apply_stokes(const wb_mesh* m, const wb_visc* v, const double* u, const double* p,
                                  double* yu, double* yp, void* stream);
-/* Reduced-precision A apply: FP32 buffers; prec = WB_FP32 (FP32 arithmetic) or
- * WB_BF16 (BF16 MFMA contractions accumulated in FP32). */
+/* Reduced-precision A apply: FP32 buffers; prec = WB_FP32 (FP32 arithmetic), WB_BF16 or
+ * WB_BF16X1 (BF16 MFMA contractions accumulated in FP32, see wb_prec). */
 WB_API wb_status wb_apply_A_lowp(const wb_mesh* m, const wb_visc* v, int prec, const float* u,
                                  float* y, void* stream);
 

@@ -278,7 +278,8 @@ wb_status wb_apply_A_lowp(const wb_mesh* mh, const wb_visc* vc, int prec, const 
   return guard([&] {
     WB_REQUIRE(mh && vc && u && y, WB_EINVAL, "NULL argument");
     WB_REQUIRE(u != y, WB_EINVAL, "in-place apply is not allowed");
-    WB_REQUIRE(prec == WB_FP32, WB_EUNSUPPORTED, "precision not built");
+    WB_REQUIRE(prec == WB_FP32 || prec == WB_BF16 || prec == WB_BF16X1, WB_EINVAL,
+               "prec must be WB_FP32, WB_BF16 or WB_BF16X1");
     const Mesh& m = mh->m;
     wb_visc* v = const_cast<wb_visc*>(vc);
     const size_t nq = (size_t)m.E * m.n * m.n * m.n;
@@ -286,8 +287,9 @@ wb_status wb_apply_A_lowp(const wb_mesh* mh, const wb_visc* vc, int prec, const 
       WB_HIP(hipMalloc(&v->mu_q_f, sizeof(float) * nq));
       launch_cast<double, float>(S(stream), nq, v->mu_q, v->mu_q_f);
     }
-    launch_op<float>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q_f, nullptr, nullptr, nullptr,
-                     false, mesh_work(mh));
+    const int mf = prec == WB_BF16 ? F_MF3 : (prec == WB_BF16X1 ? F_MF : 0);
+    launch_op<float>(S(stream), F_A | F_DIR | mf, 3, m.N, m.k, u, y,
+                     v->mu_q_f, nullptr, nullptr, nullptr, false, mesh_work(mh));
     check_launch();
     return WB_OK;
   });

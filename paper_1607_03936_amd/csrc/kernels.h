@@ -12,8 +12,11 @@ namespace wb {
 void profile_enable(bool on);
 std::string profile_summary(bool reset);
 
-// Operator flags: viscous/Poisson stiffness, gradient B^T p, divergence B u, Dirichlet mask.
-enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8 };
+// Operator flags: viscous/Poisson stiffness, gradient B^T p, divergence B u, Dirichlet mask,
+// and (FP32 data only) 1D contractions in BF16 on the matrix cores with FP32 accumulation:
+// F_MF one product of BF16-rounded operands, F_MF3 operands split into BF16 high and low parts
+// (three products).
+enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8, F_MF = 16, F_MF3 = 32 };
 
 // Sum-factorized element operator on a level with N elements/dir and order k.
 // NC = 3 (viscous stress, coef = mu) or 1 (scalar Poisson, coef = c).

@@ -167,6 +167,103 @@ __device__ __forceinline__ T Lg(int a, int q) {
   return (T)CT<n>::t.L[a * n + q];
 }
 
+// ------------------------------------------------------------ line contractions
+// A lane applies one 1D table to the n values of its line: out[q] = sum_m M[q][m] v[m], with
+// M = B (interpolation to Gauss points), Dh (collocation derivative), or their transposes.
+enum : int { C_B = 0, C_D = 1, C_BT = 2, C_DT = 3, C_NT = 4 };
+
+template <int n, typename T, int C>
+__device__ __forceinline__ T ctab(int q, int m) {
+  if constexpr (C == C_B) return Bm<n, T>(q, m);
+  else if constexpr (C == C_D) return Dm<n, T>(q, m);
+  else if constexpr (C == C_BT) return Bm<n, T>(m, q);
+  else return Dm<n, T>(m, q);
+}
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// BF16 form: the leading 4x4 block of every table goes through the matrix cores.  With the
+// 16-block 4x4x4 BF16 MFMA, lane l supplies row (l % 4) of the table as its A fragment and its
+// own 4-vector as B; each lane then receives the table times its own vector, accumulated in
+// FP32 (lanes do not mix, so any lane-to-line assignment works).  Lines of n < 4 values are
+// zero-padded; for n = 5 the fifth row and column are applied on the VALU in FP32.
+// MF = 1: one product of the BF16-rounded table and line (relative error ~2^-8 per contraction).
+// MF = 3: table and line split into BF16 high and low parts, t = t_h + t_l, v = v_h + v_l, and
+// t_h v_h + t_l v_h + t_h v_l accumulated in FP32 (~2^-16 per contraction).
+struct Frags {
+  bf16x4 f[C_NT];  // high parts
+  bf16x4 g[C_NT];  // low parts
+};
+
+template <int n>
+__device__ inline Frags make_frags() {
+  Frags fr;
+  const int row = (int)(threadIdx.x & 3);
+#pragma unroll
+  for (int c = 0; c < C_NT; ++c)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float v = 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float t = 0.f;
+        if (q < n && m < n) {
+          if (c == C_B) t = ctab<n, float, C_B>(q, m);
+          else if (c == C_D) t = ctab<n, float, C_D>(q, m);
+          else if (c == C_BT) t = ctab<n, float, C_BT>(q, m);
+          else t = ctab<n, float, C_DT>(q, m);
+        }
+        v = (row == q) ? t : v;
+      }
+      const __bf16 hi = (__bf16)v;
+      fr.f[c][m] = hi;
+      fr.g[c][m] = (__bf16)(v - (float)hi);
+    }
+  return fr;
+}
+
+template <int n, typename T, int MF, int C>
+__device__ __forceinline__ void ctr(const Frags& fr, const T (&v)[n], T (&out)[n]) {
+  if constexpr (MF == 0) {
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      T acc = T(0);
+#pragma unroll
+      for (int m = 0; m < n; ++m) acc += ctab<n, T, C>(q, m) * v[m];
+      out[q] = acc;
+    }
+  } else {
+    static_assert(sizeof(T) == 4, "the BF16 form accumulates in FP32");
+    bf16x4 bh, bl;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const float x = m < n ? v[m] : 0.f;
+      const __bf16 h = (__bf16)x;
+      bh[m] = h;
+      bl[m] = (__bf16)(x - (float)h);
+    }
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (n == 5) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[q] = ctab<5, float, C>(q, 4) * v[4];
+    }
+    d = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(fr.f[C], bh, d, 0, 0, 0);
+    if constexpr (MF == 3) {
+      d = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(fr.g[C], bh, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(fr.f[C], bl, d, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < (n < 4 ? n : 4); ++q) out[q] = d[q];
+    if constexpr (n == 5) {
+      float acc = 0.f;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) acc += ctab<5, float, C>(4, m) * v[m];
+      out[4] = acc;
+    }
+  }
+}
+
 // LDS layout of an element's scratch: value (x, y, z) at x + SY y + SZ z, slots SL apart.  The
 // strides keep the three line roles of a wavefront (z-, y- and x-lines) free of bank conflicts
 // beyond two-way (searched over padded strides for 64-lane ds_read_b64 access).
@@ -184,17 +281,19 @@ template <> struct Lds<5> { static constexpr int SY = 5, SZ = 25, SL = 125; };
 // element to its local node (x, y, z) of component c is handed to sink(c, x, y, z, value);
 // F_B writes the element's n_p pressure modes to pout.
 // Contains wavefront barriers: every lane of the wavefront must call it.
-template <int n, int NC, typename T, int F, typename Sink>
-__device__ inline void element_op(const KT<n, T>& tb, const bool valid, const int e, const int ex,
-                                  const int ey, const int ez, const int k, const int M,
-                                  const int nn, const T hh, const T* __restrict__ u,
-                                  const T* __restrict__ coef, const T* __restrict__ pin,
-                                  T* __restrict__ pout, const T* __restrict__ sin_, T* s, T* s2,
-                                  const int r, Sink&& sink) {
+template <int n, int NC, typename T, int F, int MF, typename Sink>
+__device__ inline void element_op(const bool valid, const int e, const int ex, const int ey,
+                                  const int ez, const int k, const int M, const int nn, const T hh,
+                                  const T* __restrict__ u, const T* __restrict__ coef,
+                                  const T* __restrict__ pin, T* __restrict__ pout,
+                                  const T* __restrict__ sin_, T* s, T* s2, const int r,
+                                  Sink&& sink) {
   constexpr int NN = n * n, N3 = n * n * n;
   constexpr int NP = (n - 1) * n * (n + 1) / 6;
   constexpr int SY = Lds<n>::SY, SZ = Lds<n>::SZ;
   const int a = r % n, b = r / n;
+  Frags fr;
+  if constexpr (MF) fr = make_frags<n>();
   // z-line role (i, j) = (a, b)
   const int gi = ex * k + a, gj = ey * k + b;
   const bool bij = (gi == 0) || (gi == M - 1) || (gj == 0) || (gj == M - 1);
@@ -240,65 +339,35 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
     for (int c = 0; c < NC; ++c) {
       T v[n], w[n];
       // z: interpolate the node column to the Gauss points
+      ctr<n, T, MF, C_B>(fr, uz[c], w);
 #pragma unroll
-      for (int l = 0; l < n; ++l) v[l] = uz[c][l];
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int l = 0; l < n; ++l) acc += Bm<n, T>(q, l) * v[l];
-        s[a + SY * b + SZ * q] = acc;
-      }
+      for (int q = 0; q < n; ++q) s[a + SY * b + SZ * q] = w[q];
       wave_sync();
       // y-line (a, ., b): interpolate in y, in place
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
+      ctr<n, T, MF, C_B>(fr, v, w);
 #pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm<n, T>(q, m) * v[m];
-        s[a + SY * q + SZ * b] = acc;
-      }
+      for (int q = 0; q < n; ++q) s[a + SY * q + SZ * b] = w[q];
       wave_sync();
       // x-line (., a, b): interpolate in x, then differentiate in x
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
+      ctr<n, T, MF, C_B>(fr, v, w);
+      ctr<n, T, MF, C_D>(fr, w, v);
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm<n, T>(q, m) * v[m];
-        w[q] = acc;
-      }
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm<n, T>(q, m) * w[m];
         s[q + SY * a + SZ * b] = w[q];
-        s2[q + SY * a + SZ * b] = acc;
+        s2[q + SY * a + SZ * b] = v[q];
       }
       wave_sync();
       // y-line: differentiate in y (kept); z-line: differentiate in z
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm<n, T>(q, m) * v[m];
-        w[q] = acc;
-      }
+      ctr<n, T, MF, C_D>(fr, v, w);
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s[a + SY * b + SZ * m];
-#pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm<n, T>(q, m) * v[m];
-        S[c][2][q] = acc;
-      }
+      ctr<n, T, MF, C_D>(fr, v, S[c][2]);
       wave_sync();
 #pragma unroll
       for (int q = 0; q < n; ++q) s[a + SY * q + SZ * b] = w[q];
@@ -398,13 +467,10 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
   if constexpr ((F & (F_A | F_BT)) != 0) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      T V[n], v[n];
+      T V[n], v[n], w[n];
+      ctr<n, T, MF, C_DT>(fr, S[c][2], V);
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm<n, T>(m, q) * S[c][2][m];
-        V[q] = acc;
         s[a + SY * b + SZ * q] = S[c][0][q];
         s2[a + SY * b + SZ * q] = S[c][1][q];
       }
@@ -412,67 +478,46 @@ __device__ inline void element_op(const KT<n, T>& tb, const bool valid, const in
       // x-line: transposed x-derivative of S_cx; y-line: transposed y-derivative of S_cy
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
+      ctr<n, T, MF, C_DT>(fr, v, w);
 #pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm<n, T>(m, q) * v[m];
-        s[q + SY * a + SZ * b] = acc;
-      }
+      for (int q = 0; q < n; ++q) s[q + SY * a + SZ * b] = w[q];
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s2[a + SY * m + SZ * b];
+      ctr<n, T, MF, C_DT>(fr, v, w);
 #pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dm<n, T>(m, q) * v[m];
-        s2[a + SY * q + SZ * b] = acc;
-      }
+      for (int q = 0; q < n; ++q) s2[a + SY * q + SZ * b] = w[q];
       wave_sync();
       // z-line: sum, then transposed z-interpolation to the nodes
 #pragma unroll
       for (int q = 0; q < n; ++q) V[q] += s[a + SY * b + SZ * q] + s2[a + SY * b + SZ * q];
       wave_sync();
+      ctr<n, T, MF, C_BT>(fr, V, w);
 #pragma unroll
-      for (int l = 0; l < n; ++l) {
-        T acc = T(0);
-#pragma unroll
-        for (int q = 0; q < n; ++q) acc += Bm<n, T>(q, l) * V[q];
-        s[a + SY * b + SZ * l] = acc;
-      }
+      for (int l = 0; l < n; ++l) s[a + SY * b + SZ * l] = w[l];
       wave_sync();
       // y-line (a, ., b = z node): transposed y-interpolation, in place
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
+      ctr<n, T, MF, C_BT>(fr, v, w);
 #pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm<n, T>(m, q) * v[m];
-        s[a + SY * q + SZ * b] = acc;
-      }
+      for (int q = 0; q < n; ++q) s[a + SY * q + SZ * b] = w[q];
       wave_sync();
       // x-line (., a = y node, b = z node): transposed x-interpolation to the nodes
 #pragma unroll
       for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
+      ctr<n, T, MF, C_BT>(fr, v, w);
 #pragma unroll
-      for (int q = 0; q < n; ++q) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Bm<n, T>(m, q) * v[m];
-        sink(c, q, a, b, acc);
-      }
+      for (int q = 0; q < n; ++q) sink(c, q, a, b, w[q]);
       wave_sync();
     }
   }
 }
 
 // Divergence only (no scatter): element-parallel, writes the pressure modes.
-template <int n, typename T, int F>
+template <int n, typename T, int F, int MF>
 __global__ void __launch_bounds__(256)
-k_op_gather(const KT<n, T> tb, const int N, const int k, const int M, const int E, const int nn,
-            const T hh, const T* __restrict__ u, const T* __restrict__ pout_unused,
-            T* __restrict__ pout, const T* __restrict__ sin_) {
+k_op_gather(const int N, const int k, const int M, const int E, const int nn, const T hh,
+            const T* __restrict__ u, T* __restrict__ pout, const T* __restrict__ sin_) {
   constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n>::SL;
   __shared__ T sm[2 * (SLOTS + 1) * SL];
   int slot, r;
@@ -488,8 +533,8 @@ k_op_gather(const KT<n, T> tb, const int N, const int k, const int M, const int 
     ez = q / N;
   }
   T* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
-  element_op<n, 3, T, F>(tb, valid, e, ex, ey, ez, k, M, nn, hh, u, nullptr, nullptr, pout, sin_, s0,
-                         s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
+  element_op<n, 3, T, F, MF>(valid, e, ex, ey, ez, k, M, nn, hh, u, nullptr, nullptr, pout, sin_, s0,
+                             s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
 }
 
 // Brick geometry of the scatter kernel: a block owns a BX x BY tile of elements and marches
@@ -582,9 +627,9 @@ struct BrickThreads {
   static constexpr int NT = 64 * WAVES;
 };
 
-template <int n, int NC, typename T, int F>
+template <int n, int NC, typename T, int F, int MF>
 __global__ void __launch_bounds__(BrickThreads<n>::NT)
-k_op_brick(const KT<n, T> tb, const BrickGeom G, const T hh, const T* __restrict__ u,
+k_op_brick(const BrickGeom G, const T hh, const T* __restrict__ u,
            T* __restrict__ y, const T* __restrict__ coef, const T* __restrict__ pin,
            T* __restrict__ pout, const T* __restrict__ sin_, T* __restrict__ face, const int add) {
   constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY, NE = BX * BY;
@@ -614,8 +659,8 @@ k_op_brick(const KT<n, T> tb, const BrickGeom G, const T hh, const T* __restrict
     const int e = ex + N * (ey + N * ez);
     T* wbase = win + (ly * k) * WX + lx * k;
     T* s0 = sm + (lane_ok ? le : SLOTS) * SL;
-    element_op<n, NC, T, F>(tb, valid, e, ex, ey, ez, k, M, G.nn, hh, u, coef, pin, pout, sin_, s0,
-                            s0 + (SLOTS + 1) * SL, r, [&](int c, int x, int yy, int z, T v) {
+    element_op<n, NC, T, F, MF>(valid, e, ex, ey, ez, k, M, G.nn, hh, u, coef, pin, pout, sin_, s0,
+                                s0 + (SLOTS + 1) * SL, r, [&](int c, int x, int yy, int z, T v) {
                               if (valid) atomicAdd(wbase + (c * (k + 1) + z) * WP + yy * WX + x, v);
                             });
     __syncthreads();
@@ -741,61 +786,81 @@ std::string op_key(int NC, int k, int N, int F, bool scale, size_t es, const cha
   char key[160];
   snprintf(key, sizeof(key), "op%s nc=%d k=%d N=%d flags=%s%s%s%s%s %s", part, NC, k, N,
            (F & F_A) ? "A" : "", (F & F_BT) ? "+BT" : "", (F & F_B) ? "+B" : "",
-           (F & F_DIR) ? "+dir" : "", scale ? "+scale" : "", es == 8 ? "f64" : "f32");
+           (F & F_DIR) ? "+dir" : "", scale ? "+scale" : "",
+           es == 8 ? "f64" : ((F & F_MF3) ? "f32+bf16x3mfma" : ((F & F_MF) ? "f32+bf16mfma" : "f32")));
   return key;
 }
 
-template <int n, int NC, typename T, int F>
+template <int n, int NC, typename T, int F, int MF>
 void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, const T* pin, T* pout,
                const T* sin, bool add, void* work) {
   const int M = k * N + 1, E = N * N * N, nn = M * M * M;
   const T hh = (T)(0.5 / N);
-  const KT<n, T> tb = make_kt<n, T>(k);
+  const int Fk = F | (MF == 1 ? F_MF : 0) | (MF == 3 ? F_MF3 : 0);
   if constexpr ((F & (F_A | F_BT)) == 0) {
     constexpr int SLOTS = 4 * WaveMap<n>::EPW;
-    ProfScope ps(st, op_key(NC, k, N, F, sin != nullptr, sizeof(T), ""));
-    hipLaunchKernelGGL((k_op_gather<n, T, F>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, tb, N, k,
-                       M, E, nn, hh, u, nullptr, pout, sin);
+    ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
+    hipLaunchKernelGGL((k_op_gather<n, T, F, MF>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, N, k,
+                       M, E, nn, hh, u, pout, sin);
   } else {
     constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY;
     const BrickGeom G = brick_geom(N, k, BX, BY);
     T* face = static_cast<T*>(work);
     {
-      ProfScope ps(st, op_key(NC, k, N, F, sin != nullptr, sizeof(T), ""));
-      hipLaunchKernelGGL((k_op_brick<n, NC, T, F>), dim3(G.nbx * G.nby, G.nbz),
-                         dim3(BrickThreads<n>::NT), 0, st, tb, G, hh, u, y, coef, pin, pout, sin,
-                         face, (int)add);
+      ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
+      hipLaunchKernelGGL((k_op_brick<n, NC, T, F, MF>), dim3(G.nbx * G.nby, G.nbz),
+                         dim3(BrickThreads<n>::NT), 0, st, G, hh, u, y, coef, pin, pout, sin, face,
+                         (int)add);
     }
     const size_t tot = (size_t)(G.nbx + G.nby + G.nbz - 3) * G.plane;
     if (tot > 0) {
-      ProfScope ps(st, op_key(NC, k, N, F, sin != nullptr, sizeof(T), "-faces"));
+      ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), "-faces"));
       hipLaunchKernelGGL((k_face_sum<NC, T, (F & F_DIR) != 0>), dim3(grid_for(tot, 256)), dim3(256),
                          0, st, G, face, y, (int)add);
     }
   }
 }
 
-template <int n, typename T>
-void op_dispatch_n(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
-                   const T* pin, T* pout, const T* sin, bool add, void* work) {
+template <int n, typename T, int MF>
+void op_dispatch_mf(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y,
+                    const T* coef, const T* pin, T* pout, const T* sin, bool add, void* work) {
   if (NC == 1) {
-    if (flags == F_A) return op_launch<n, 1, T, F_A>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+    if (flags == F_A)
+      return op_launch<n, 1, T, F_A, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
   } else {
     switch (flags) {
       case F_A | F_DIR:
-        return op_launch<n, 3, T, F_A | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+        return op_launch<n, 3, T, F_A | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
       case F_A | F_BT | F_B | F_DIR:
-        return op_launch<n, 3, T, F_A | F_BT | F_B | F_DIR>(st, N, k, u, y, coef, pin, pout, sin,
-                                                             add, work);
+        if constexpr (MF == 0)
+          return op_launch<n, 3, T, F_A | F_BT | F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout,
+                                                                  sin, add, work);
+        break;
       case F_B | F_DIR:
-        return op_launch<n, 3, T, F_B | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+        return op_launch<n, 3, T, F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
       case F_BT | F_DIR:
-        return op_launch<n, 3, T, F_BT | F_DIR>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+        return op_launch<n, 3, T, F_BT | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
       default:
         break;
     }
   }
   throw Error{WB_EUNSUPPORTED, "operator flag combination not built"};
+}
+
+template <int n, typename T>
+void op_dispatch_n(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
+                   const T* pin, T* pout, const T* sin, bool add, void* work) {
+  if ((flags & (F_MF | F_MF3)) != 0) {
+    if constexpr (sizeof(T) == 4) {
+      if ((flags & F_MF3) != 0)
+        return op_dispatch_mf<n, T, 3>(st, flags & ~(F_MF | F_MF3), NC, N, k, u, y, coef, pin, pout,
+                                       sin, add, work);
+      return op_dispatch_mf<n, T, 1>(st, flags & ~F_MF, NC, N, k, u, y, coef, pin, pout, sin, add,
+                                     work);
+    }
+    throw Error{WB_EUNSUPPORTED, "BF16 contractions are built for FP32 data only"};
+  }
+  return op_dispatch_mf<n, T, 0>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
 }
 
 // ------------------------------------------------------------------ diagonals

@@ -216,9 +216,9 @@ std::vector<double> make_bhat(int k) {
 }
 
 template <typename T>
-void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out, void* work) {
-  launch_op<T>(st, L.dir ? (F_A | F_DIR) : F_A, L.NC, L.N, L.k, in, out, L.coef, nullptr, nullptr,
-               nullptr, false, work);
+void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out, void* work, int extra = 0) {
+  launch_op<T>(st, (L.dir ? (F_A | F_DIR) : F_A) | extra, L.NC, L.N, L.k, in, out, L.coef, nullptr,
+               nullptr, nullptr, false, work);
 }
 
 // Chebyshev-accelerated Jacobi (degree steps) for A x = b, A given as a callback.
@@ -461,6 +461,16 @@ double dot_host(Solver& s, size_t n, const double* x, const double* y) {
 }
 
 // ------------------------------------------------------------------ applies
+// Operator flag of the preconditioner's precision: FP32 data with BF16 matrix-core contractions
+// (split operands for WB_BF16, single products for WB_BF16X1).
+template <typename T>
+inline int mf_flag(const Solver& s) {
+  if (sizeof(T) != 4) return 0;
+  if (s.o.precond_prec == WB_BF16) return F_MF3;
+  if (s.o.precond_prec == WB_BF16X1) return F_MF;
+  return 0;
+}
+
 template <typename T>
 void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
   hipStream_t st = s.st;
@@ -470,7 +480,7 @@ void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
     launch_dense<T>(st, H.nd, H.G, H.gidx, b, x);
     return;
   }
-  auto op = [&](const T* in, T* out) { level_op<T>(st, L, in, out, s.opwork); };
+  auto op = [&](const T* in, T* out) { level_op<T>(st, L, in, out, s.opwork, mf_flag<T>(s)); };
   const int deg = s.o.cheb_degree;
   chebyshev<T>(st, op, L.len, L.dinv, L.lmin, L.lmax, deg, b, x, true, L.r, L.d, L.t);
   op(x, L.t);
@@ -491,9 +501,9 @@ template <typename T>
 void apply_K(Solver& s, Precond<T>& P, int side, const T* p, T* y) {
   hipStream_t st = s.st;
   const Mesh& m = s.m;
-  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr, nullptr, false,
+  launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr, nullptr, false,
                s.opwork);
-  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y, P.winv[side], false,
+  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y, P.winv[side], false,
                nullptr);
 }
 
@@ -528,11 +538,11 @@ void apply_wbfbt(Solver& s, Precond<T>& P, const T* r, T* z) {
   launch_remove_mean<T>(st, m.E, m.np, P.pb, s.red_partial, s.red_out + 2);
   apply_vcycle_K<T>(s, P, 1, P.pb, P.py);
   // middle product B C^-1 A D^-1 B^T
-  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, P.py, nullptr, nullptr, false,
+  launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.v1, nullptr, P.py, nullptr, nullptr, false,
                s.opwork);
-  launch_op<T>(st, F_A | F_DIR, 3, m.N, m.k, P.v1, P.v2, fine_mu(s, P), nullptr, nullptr, P.winv[1],
+  launch_op<T>(st, F_A | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v1, P.v2, fine_mu(s, P), nullptr, nullptr, P.winv[1],
                false, s.opwork);
-  launch_op<T>(st, F_B | F_DIR, 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, P.winv[0], false,
+  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, P.winv[0], false,
                nullptr);
   launch_remove_mean<T>(st, m.E, m.np, P.pm, s.red_partial, s.red_out + 2);
   apply_vcycle_K<T>(s, P, 0, P.pm, z);
@@ -549,7 +559,7 @@ void apply_precond(Solver& s, Precond<T>& P, const T* ru, const T* rp, T* zu, T*
   const Mesh& m = s.m;
   const size_t vl = (size_t)3 * m.nn;
   apply_wbfbt<T>(s, P, rp, zp);
-  launch_op<T>(st, F_BT | F_DIR, 3, m.N, m.k, nullptr, P.v1, nullptr, zp, nullptr, nullptr, false,
+  launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.v1, nullptr, zp, nullptr, nullptr, false,
                s.opwork);
   launch_sub<T>(st, vl, ru, P.v1, P.v2);
   apply_vcycle_A<T>(s, P, P.v2, zu);
@@ -595,7 +605,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
              "bad solver options");
   WB_REQUIRE(o.a_l >= 1.0 && o.a_r >= 1.0, WB_EINVAL, "boundary amplification must be >= 1");
   WB_REQUIRE(o.p_schedule == 0 || o.p_schedule == 1, WB_EINVAL, "p_schedule must be 0 or 1");
-  WB_REQUIRE(o.precond_prec == WB_FP64 || o.precond_prec == WB_FP32, WB_EUNSUPPORTED,
+  WB_REQUIRE(o.precond_prec >= WB_FP64 && o.precond_prec <= WB_BF16X1, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
   std::unique_ptr<Solver> sp(new Solver());
@@ -654,7 +664,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     P.klmin[side] = 0.1 * lam;
     P.klmax[side] = 1.1 * lam;
   }
-  if (o.precond_prec == WB_FP32) {
+  if (o.precond_prec != WB_FP64) {
     s.pf.reset(new Precond<float>());
     Precond<float>& F = *s.pf;
     cast_hierarchy(s, P.A, F.A);

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwbfbt.so")
 
 WB_OK, WB_EINVAL, WB_ENOMEM, WB_EHIP, WB_ENOCONV, WB_ENAN, WB_EUNSUPPORTED = range(7)
-WB_FP64, WB_FP32, WB_BF16 = 0, 1, 2
+WB_FP64, WB_FP32, WB_BF16, WB_BF16X1 = 0, 1, 2, 3
 
 
 class WbError(RuntimeError):

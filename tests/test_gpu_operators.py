@@ -128,6 +128,39 @@ def test_apply_A_fp32_error_is_single_precision():
     assert 1e-9 < err < 1e-5
 
 
+@pytest.mark.parametrize("N,k", CASES)
+@pytest.mark.parametrize("form", ["bf16x1", "bf16x3"])
+def test_apply_A_bf16_mfma_error(N, k, form):
+    """BF16 forms: every 1D contraction runs on the BF16 matrix cores with FP32 accumulation.
+    A value passes through six contractions (three forward, three transposed).  bf16x1 rounds the
+    table and the line to BF16 (unit roundoff 2^-9 each), so the relative error is a few times
+    6 * 2 * 2^-9 ~ 2.3e-2 at most; bf16x3 keeps high and low BF16 parts of both and drops only the
+    low x low product and the rounding of the low parts (~2^-16 per contraction, ~2e-4 for six).
+    Both must stay above the FP32 level (~1e-7), which shows the matrix-core path ran."""
+    wb = _wb()
+    om = fem.Mesh(N, k)
+    rng = np.random.default_rng(3)
+    mu_q = np.exp(rng.uniform(-3, 3, (om.E, om.n ** 3)))
+    m = wb.Mesh(N, k)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(np.ones(om.n_nodes)))
+    u = random_vector(4, om.u_dof)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0
+    want = fem.assemble_A(om, mu_q) @ ui
+    want[om.vel_boundary] = 0
+    y = torch.empty(m.u_len, dtype=torch.float32, device="cuda")
+    prec = wb.WB_BF16X1 if form == "bf16x1" else wb.WB_BF16
+    wb.wb_apply_A_lowp(m, v, prec, dev(u).float(), y)
+    yh = host(y).astype(np.float64)
+    err = np.linalg.norm(yh - want) / np.linalg.norm(want)
+    print(f"{form} A apply N={N} k={k}: relative error {err:.3e}")
+    assert np.all(yh[om.vel_boundary] == 0.0)
+    if form == "bf16x1":
+        assert 1e-4 < err < 2.5e-2
+    else:
+        assert 3e-7 < err < 2e-4
+
+
 @pytest.mark.parametrize("name", ["c2", "c5"])
 def test_apply_A_full_size_sampled_rows(name):
     # the workload sizes, checked on sampled rows computed element by element by the oracle

@@ -187,3 +187,34 @@ def test_graph_replayed_preconditioner_matches_eager(prec):
         assert rg.rel_res <= 1e-6
         assert _rel(host(ug), host(ue)) < tol
         assert _rel(host(pg), host(pe)) < tol
+
+
+@pytest.mark.parametrize("name", ["n8k2", "n4k4"])
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x1"])
+def test_bf16_mfma_preconditioner_reaches_tolerance(name, form):
+    """Preconditioner applies in FP32 with BF16 matrix-core contractions; FP64 FGMRES, weights,
+    diagonals and coarsest solve.  The outer solve still reaches 1e-6 and its solution agrees
+    with the FP64-preconditioned one to the accuracy the tolerance allows.  With split operands
+    the iteration count stays at the FP64 count; single BF16 products cost iterations."""
+    wb = _wb()
+    w, st, P, m, v, s = _pair(name)
+    om = st.mesh
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    u64 = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    p64 = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    r64 = s.solve(f, u64, p64)
+    prec = wb.WB_BF16 if form == "bf16x3" else wb.WB_BF16X1
+    sb = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, precond_prec=prec)
+    ub = torch.empty_like(u64)
+    pb = torch.empty_like(p64)
+    rb = sb.solve(f, ub, pb)
+    du = np.linalg.norm(host(ub) - host(u64)) / np.linalg.norm(host(u64))
+    dp = np.linalg.norm(host(pb) - host(p64)) / np.linalg.norm(host(p64))
+    print(f"{name} {form}: FP64 {r64.iters} its, BF16 {rb.iters} its, du {du:.2e} dp {dp:.2e}")
+    assert rb.rel_res <= 1e-6
+    assert du < 1e-4 and dp < 1e-3
+    if form == "bf16x3":
+        assert rb.iters <= r64.iters + 3
+    else:
+        assert rb.iters <= 2 * r64.iters + 5
