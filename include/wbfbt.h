@@ -83,6 +83,10 @@ typedef struct {
   int use_graph;          /* 1: wb_solve replays the preconditioner apply from a
                              HIP graph captured at its first iteration (default);
                              0: every launch is issued from the host             */
+  int schur_sign;         /* sign of the Schur block of the preconditioner (eq. 3):
+                             -1 (default): -S~, the saddle matrix's own Schur
+                             complement sign (the paper's S is its negation);
+                             +1: eq. (3) as printed                              */
 } wb_opts;
 
 typedef struct {
@@ -196,16 +200,74 @@ WB_API wb_status wb_solver_query(wb_solver* s, int what, int level, double* out_
 WB_API wb_status wb_solver_levels(wb_solver* s, int which, int* nlevels, int* Ns, int* ks, double* lmax);
 
 /* ---- learned coarse correction (velocity V-cycle, level Q1 on N/2) ----
- * A small FP32 3D convolutional network N_theta maps (log10 mu_c, r_c/|r_c|) on
- * the coarse node grid to e_c/|r_c|.  Training pairs (r_c, A_c^-1 r_c) are
- * generated by the library on the seeded sinker fields given; training runs
- * on the GPU with the library's own forward/backward kernels and Adam. */
-WB_API wb_status wb_learned_train(wb_solver* s, const double* centers_host, const int* n_sinkers,
-                                  int n_fields, int pairs_per_field, int epochs, double lr,
-                                  double* final_loss, void* stream);
-/* Flat FP32 parameter blob: query size with params == NULL. HOST pointers. */
+ * The paper has no learned component; this is the data-driven counterpart of its multigrid
+ * smoothing (Sec. 6) used as an optional extra step.  At the velocity level lc = Q1 on N/2
+ * elements per direction (M = N/2 + 1 nodes per direction), after the plain V-cycle there:
+ *   r = b - A_c x,  rho = rms(r),  delta = rho N_theta(f, r / rho) / diag(A_c)  (0 on the boundary),
+ *   x <- x + alpha delta,  alpha = clip((r, A_c delta) / (A_c delta, A_c delta), 0, 2),
+ * so the step never increases the residual and alpha = 0 is the plain V-cycle (a rejected step).
+ * f is the node feature (mean log10 mu of the adjacent elements, / 5).  N_theta: FP32 3x3x3
+ * convolutions with zero padding, 4 -> 16 -> 16 -> 16 -> 3 channels, leaky ReLU (slope 0.1).
+ * It is used by wb_solve when opts.use_learned = 1 and the network is trained or set; FGMRES
+ * switches it off for the rest of a solve when the residual falls by less than half over 20
+ * iterations (wb_report.fell_back counts rejected steps plus such a switch-off). */
+typedef struct {
+  int pairs_per_field;    /* training pairs per viscosity field (8)                       */
+  int vcycles;            /* plain V-cycles applied to each random start error (1)        */
+  int epochs;             /* passes over the training pairs (20)                          */
+  int batch;              /* pairs per Adam step (8)                                      */
+  double lr;              /* Adam step size (1e-3; beta 0.9, 0.999, eps 1e-8)             */
+  unsigned long long seed;/* splitmix64 seed of start errors, initial weights, shuffles   */
+  double delta, omega, mu_min, mu_max;  /* sinker parameters of the training fields       */
+  int n_valid;            /* trailing fields held out for the validation loss (0)         */
+} wb_train_opts;
+
+typedef struct {
+  double loss_first, loss_last;  /* mean training loss of the first and last epoch        */
+  double valid_loss;             /* mean loss on the held-out fields (0 if none)          */
+  double t_pairs_s, t_train_s;   /* wall time of pair generation and of the Adam epochs   */
+  long long n_params;
+  int n_pairs;
+} wb_train_report;
+
+WB_API void wb_train_opts_default(wb_train_opts* o);
+/* Train the network of solver s on its GPU.  Field f has n_sinkers[f] sinker centers, stored
+ * after those of fields 0..f-1 in centers_host ([sum n_sinkers][3], HOST).  For each field the
+ * library evaluates the sinker viscosity on the solver's mesh, coarsens it to levels lc.. like
+ * the solver's own hierarchy (diagonals, Chebyshev bounds per field; the coarsest direct solve
+ * is the solver's), and forms pairs: e = (I - V A_c)^vcycles e0 with e0 a splitmix64 field,
+ * r = A_c e, target d e / rho and weight rho^2 / (d sum_j d_j e_j^2) (d = diag A_c) for the loss
+ * (1/B) sum w (N_theta - t)^2 (N_theta = 0 scores 1).  Then Adam over shuffled batches, from
+ * fresh He-uniform weights with a zero output layer.
+ * Synchronizes the stream.  WB_EUNSUPPORTED if the mesh has no level Q1 on N/2 above the
+ * coarsest; WB_EINVAL for bad options. */
+WB_API wb_status wb_learned_train(wb_solver* s, int n_fields, const int* n_sinkers,
+                                  const double* centers_host, const wb_train_opts* opts,
+                                  wb_train_report* rep, void* stream);
+/* Flat FP32 parameter blob (HOST pointers): per layer W [Cout][Cin][27] (tap dx + 3 dy + 9 dz
+ * multiplies the input at offset (dx-1, dy-1, dz-1)), then b [Cout].  get: size query with
+ * params == NULL.  set: n_params must match; marks the network trained. */
 WB_API wb_status wb_learned_get(wb_solver* s, float* params, long long* n_params);
 WB_API wb_status wb_learned_set(wb_solver* s, const float* params, long long n_params);
+/* Level index lc in the velocity hierarchy, nodes per direction M there, parameter count. */
+WB_API wb_status wb_learned_info(wb_solver* s, int* level, int* M, long long* n_params);
+/* The correction step for a given residual r at level lc ([3][M^3], FP64, device): writes
+ * delta (device) and alpha (HOST) without applying it. */
+WB_API wb_status wb_learned_probe(wb_solver* s, const double* r, double* delta, double* alpha,
+                                  void* stream);
+
+/* Network kernels on caller data (all device pointers, FP32, fields [b][channel][z][y][x]):
+ * x [B][4][M^3] -> out [B][3][M^3]; with t, w [B][3][M^3] and grad [n_params] also the loss
+ * (1/B) sum w (out - t)^2 (HOST *loss) and its parameter gradient (t, w, grad all or none).
+ * Allocates its work space.  wb_net_adam: one bias-corrected Adam step (step >= 1) on params
+ * with moments m, v.  wb_net_feature: node feature of a Q1 coefficient [N^3][8] (FP64) on
+ * (N+1)^3 nodes. */
+WB_API long long wb_net_param_count(void);
+WB_API wb_status wb_net_eval(int M, int B, const float* params, const float* x, const float* t,
+                             const float* w, float* out, float* grad, double* loss, void* stream);
+WB_API wb_status wb_net_adam(long long n, float* params, const float* grad, float* m, float* v,
+                             int step, double lr, void* stream);
+WB_API wb_status wb_net_feature(int N, const double* coef, float* feat, void* stream);
 
 /* ---- instrumentation ----
  * When enabled, every operator-kernel launch is bracketed by HIP events on the

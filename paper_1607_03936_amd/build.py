@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwbfbt.so")
-SOURCES = ["tables.cpp", "kernels.hip", "solver.hip", "api.hip"]
+SOURCES = ["tables.cpp", "kernels.hip", "learned.hip", "solver.hip", "api.hip"]
 ARCH = os.environ.get("WB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -95,6 +95,7 @@ void wb_opts_default(wb_opts* o) {
   o->use_learned = 0;
   o->verbose = 0;
   o->use_graph = 1;
+  o->schur_sign = -1;
 }
 
 const char* wb_last_error(void) { return g_err.c_str(); }
@@ -482,25 +483,158 @@ wb_status wb_apply_A_add(const wb_mesh* mh, const wb_visc* v, const double* u, d
   });
 }
 
-wb_status wb_learned_train(wb_solver* sh, const double*, const int*, int, int, int, double, double*,
-                           void*) {
+void wb_train_opts_default(wb_train_opts* o) {
+  if (!o) return;
+  const TrainOpts d;
+  o->pairs_per_field = d.pairs_per_field;
+  o->vcycles = d.vcycles;
+  o->epochs = d.epochs;
+  o->batch = d.batch;
+  o->lr = d.lr;
+  o->seed = d.seed;
+  o->delta = d.delta;
+  o->omega = d.omega;
+  o->mu_min = d.mu_min;
+  o->mu_max = d.mu_max;
+  o->n_valid = d.n_valid;
+}
+
+wb_status wb_learned_train(wb_solver* sh, int n_fields, const int* n_sinkers,
+                           const double* centers_host, const wb_train_opts* opts,
+                           wb_train_report* rep, void* stream) {
   return guard([&] {
-    (void)SV(sh);
-    throw Error{WB_EUNSUPPORTED, "learned coarse correction not built"};
+    Solver& s = SV(sh);
+    WB_REQUIRE(opts && n_sinkers, WB_EINVAL, "NULL argument");
+    s.st = S(stream);
+    TrainOpts o;
+    o.pairs_per_field = opts->pairs_per_field;
+    o.vcycles = opts->vcycles;
+    o.epochs = opts->epochs;
+    o.batch = opts->batch;
+    o.lr = opts->lr;
+    o.seed = opts->seed;
+    o.delta = opts->delta;
+    o.omega = opts->omega;
+    o.mu_min = opts->mu_min;
+    o.mu_max = opts->mu_max;
+    o.n_valid = opts->n_valid;
+    TrainReport r;
+    learned_train(s, n_fields, n_sinkers, centers_host, o, &r);
+    check_launch();
+    if (rep) {
+      rep->loss_first = r.loss_first;
+      rep->loss_last = r.loss_last;
+      rep->valid_loss = r.valid_loss;
+      rep->t_pairs_s = r.t_pairs_s;
+      rep->t_train_s = r.t_train_s;
+      rep->n_params = r.n_params;
+      rep->n_pairs = r.n_pairs;
+    }
     return WB_OK;
   });
 }
-wb_status wb_learned_get(wb_solver* sh, float*, long long*) {
+
+wb_status wb_learned_get(wb_solver* sh, float* params, long long* n_params) {
   return guard([&] {
-    (void)SV(sh);
-    throw Error{WB_EUNSUPPORTED, "learned coarse correction not built"};
+    Solver& s = SV(sh);
+    WB_REQUIRE(s.learned, WB_EUNSUPPORTED, "no learned level (Q1 on N/2) on this mesh");
+    if (n_params) *n_params = (long long)net_param_count();
+    if (params) {
+      WB_HIP(hipMemcpy(params, s.learned->params, sizeof(float) * net_param_count(),
+                       hipMemcpyDeviceToHost));
+    }
     return WB_OK;
   });
 }
-wb_status wb_learned_set(wb_solver* sh, const float*, long long) {
+
+wb_status wb_learned_set(wb_solver* sh, const float* params, long long n_params) {
   return guard([&] {
-    (void)SV(sh);
-    throw Error{WB_EUNSUPPORTED, "learned coarse correction not built"};
+    Solver& s = SV(sh);
+    WB_REQUIRE(params, WB_EINVAL, "NULL parameters");
+    WB_REQUIRE(n_params == (long long)net_param_count(), WB_EINVAL, "parameter count mismatch");
+    learned_set(s, params);
+    return WB_OK;
+  });
+}
+
+wb_status wb_learned_info(wb_solver* sh, int* level, int* M, long long* n_params) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(s.learned, WB_EUNSUPPORTED, "no learned level (Q1 on N/2) on this mesh");
+    if (level) *level = s.learned->lc;
+    if (M) *M = s.learned->M;
+    if (n_params) *n_params = (long long)net_param_count();
+    return WB_OK;
+  });
+}
+
+wb_status wb_learned_probe(wb_solver* sh, const double* r, double* delta, double* alpha,
+                           void* stream) {
+  return guard([&] {
+    Solver& s = SV(sh);
+    WB_REQUIRE(r && delta && alpha && r != delta, WB_EINVAL, "bad arguments");
+    s.st = S(stream);
+    learned_probe(s, r, delta, alpha);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+long long wb_net_param_count(void) { return (long long)net_param_count(); }
+
+wb_status wb_net_eval(int M, int B, const float* params, const float* x, const float* t,
+                      const float* w, float* out, float* grad, double* loss, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(M >= 2 && M <= 1025 && B >= 1, WB_EINVAL, "bad grid or batch");
+    WB_REQUIRE(params && x && out, WB_EINVAL, "NULL argument");
+    WB_REQUIRE((t == nullptr) == (w == nullptr) && (grad == nullptr) == (t == nullptr), WB_EINVAL,
+               "t, w and grad must be given together");
+    hipStream_t st = S(stream);
+    void* base = nullptr;
+    WB_HIP(hipMalloc(&base, net_work_bytes(M, B)));
+    double* dl = nullptr;
+    if (hipMalloc(&dl, sizeof(double)) != hipSuccess) {
+      (void)hipFree(base);
+      throw Error{WB_ENOMEM, "hipMalloc failed"};
+    }
+    NetWork nw;
+    net_work_carve(nw, M, B, base);
+    net_forward(st, params, x, nw);
+    if (t) net_backward(st, params, x, t, w, nw, grad, dl);
+    const size_t n = (size_t)B * 3 * M * M * M;
+    hipError_t e = hipMemcpyAsync(out, nw.z[3], sizeof(float) * n, hipMemcpyDeviceToDevice, st);
+    double lh = 0.0;
+    if (e == hipSuccess && t) e = hipMemcpyAsync(&lh, dl, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(base);
+    (void)hipFree(dl);
+    if (e != hipSuccess) throw Error{WB_EHIP, hipGetErrorString(e)};
+    if (loss) *loss = lh;
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_net_adam(long long n, float* params, const float* grad, float* m, float* v, int step,
+                      double lr, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(n > 0 && params && grad && m && v && step >= 1 && lr > 0, WB_EINVAL, "bad arguments");
+    net_adam(S(stream), (size_t)n, params, grad, m, v, step, (float)lr);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_net_feature(int N, const double* coef, float* feat, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(N >= 1 && N <= 1024 && coef && feat, WB_EINVAL, "bad arguments");
+    float* tmp = nullptr;
+    WB_HIP(hipMalloc(&tmp, sizeof(float) * (size_t)N * N * N));
+    launch_node_feature(S(stream), N, coef, feat, tmp);
+    const hipError_t e = hipStreamSynchronize(S(stream));
+    (void)hipFree(tmp);
+    if (e != hipSuccess) throw Error{WB_EHIP, hipGetErrorString(e)};
+    check_launch();
     return WB_OK;
   });
 }

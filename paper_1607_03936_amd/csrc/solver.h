@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "learned.h"
 
 namespace wb {
 
@@ -37,6 +38,7 @@ struct Level {
   double lmin = 0, lmax = 0;
   T *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
   Rows1D P{}, R{};         // prolongation from / restriction to the next coarser level
+  double* Q = nullptr;     // coefficient coarsening matrix from the next finer level
 };
 
 template <typename T>
@@ -68,6 +70,20 @@ struct Precond {
   T *cin_u = nullptr, *cin_p = nullptr, *cout_u = nullptr, *cout_p = nullptr;  // casts (FP32)
 };
 
+// Learned coarse correction state: network parameters, the node feature of the solver's
+// viscosity at the velocity level lc (Q1 on N/2), inference buffers and device counters.
+struct Learned {
+  int lc = -1, M = 0;
+  bool trained = false;
+  bool active = true;          // false while training pairs are generated / after stagnation
+  float* params = nullptr;     // [net_param_count()]
+  float* feat = nullptr;       // [M^3]
+  float* xin = nullptr;        // [4][M^3]
+  float* elem_tmp = nullptr;   // [(M-1)^3]
+  NetWork w1;                  // batch-1 inference buffers
+  int* counters = nullptr;     // [2]: accepted, rejected correction steps
+};
+
 struct Solver {
   Mesh m;
   wb_opts o;
@@ -89,7 +105,7 @@ struct Solver {
   hipGraphExec_t pgraph = nullptr;
   double *gin = nullptr, *gout = nullptr;
   // learned correction (optional)
-  struct Learned* learned = nullptr;
+  std::unique_ptr<Learned> learned;
   int learned_used = 0, fell_back = 0;
   ~Solver();
 };
@@ -114,6 +130,28 @@ void apply_precond_any(Solver& s, const double* ru, const double* rp, double* zu
 wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep);
 // GMRES on one block with its V-cycle: which = 0 (A u = f), 1 (K_l p = g), 2 (K_r p = g).
 wb_status subsolve(Solver& s, int which, const double* b, double* x, wb_report* rep);
+
+// Training of the learned coarse correction on seeded sinker fields (centers of field f at
+// centers + 3 * sum_{g<f} n_sinkers[g]); see wb_learned_train.
+struct TrainOpts {
+  int pairs_per_field = 8, vcycles = 1, epochs = 20, batch = 8;
+  double lr = 1e-3;
+  unsigned long long seed = 1000;
+  double delta = 200, omega = 0.1, mu_min = 1e-3, mu_max = 1e3;
+  int n_valid = 0;  // trailing fields held out for the validation loss
+};
+struct TrainReport {
+  double loss_first = 0, loss_last = 0, valid_loss = 0;
+  double t_pairs_s = 0, t_train_s = 0;
+  long long n_params = 0;
+  int n_pairs = 0;
+};
+void learned_train(Solver& s, int n_fields, const int* n_sinkers, const double* centers,
+                   const TrainOpts& o, TrainReport* rep);
+// Guarded correction at level lc for a given residual r (FP64): delta and alpha, no update.
+void learned_probe(Solver& s, const double* r, double* delta, double* alpha_host);
+// Replace the parameters (device copy from host) and mark the network trained.
+void learned_set(Solver& s, const float* params_host);
 
 // host helpers
 double dot_host(Solver& s, size_t n, const double* x, const double* y);

@@ -275,6 +275,33 @@ double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, cons
   return tridiag_max_eig(dg, off);
 }
 
+// Chebyshev interval [0.1, 1.1] * lambda_max(D^-1 A) of a level, lambda_max from Jacobi-CG
+// (Lanczos) steps started from the splitmix64 vector of `seed` (Dirichlet entries zeroed, or
+// the mean removed for the Neumann Poisson levels).
+void set_cheb_bounds(Solver& s, Level<double>& L, unsigned long long seed) {
+  hipStream_t st = s.st;
+  std::vector<double> b0;
+  splitmix_vector(seed, L.len, b0);
+  const int M = L.k * L.N + 1;
+  if (L.dir) {
+    for (size_t i = 0; i < L.len; ++i) {
+      const size_t g = i % L.nn;
+      const int gi = (int)(g % M), gj = (int)((g / M) % M), gl = (int)(g / ((size_t)M * M));
+      if (gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1 || gl == 0 || gl == M - 1) b0[i] = 0.0;
+    }
+  } else {
+    double mean = 0.0;
+    for (double v : b0) mean += v;
+    mean /= (double)b0.size();
+    for (double& v : b0) v -= mean;
+  }
+  auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out, s.opwork); };
+  const double lam = lanczos_max(s, op, L.len, L.dinv, b0, s.o.lanczos_steps, L.x, L.b, L.r, L.d);
+  L.lmin = 0.1 * lam;
+  L.lmax = 1.1 * lam;
+  for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
+}
+
 // Build an FP64 hierarchy on `coef0` (velocity if NC == 3, Poisson if NC == 1).
 void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef0, int seed_base) {
   hipStream_t st = s.st;
@@ -300,14 +327,14 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
       const Level<double>& F = H.L[li - 1];
       if (F.N == L.N) {
         auto Q = coarsen_matrix(F.k + 1, n, 1);
-        double* dQ = ar.alloc<double>(Q.size());
-        WB_HIP(hipMemcpy(dQ, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
-        launch_coarsen_p(st, L.E, F.k + 1, n, dQ, F.coef, L.coef);
+        L.Q = ar.alloc<double>(Q.size());
+        WB_HIP(hipMemcpy(L.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
+        launch_coarsen_p(st, L.E, F.k + 1, n, L.Q, F.coef, L.coef);
       } else {
         auto Q = coarsen_matrix(n, n, 2);
-        double* dQ = ar.alloc<double>(Q.size());
-        WB_HIP(hipMemcpy(dQ, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
-        launch_coarsen_h(st, F.N, n, dQ, F.coef, L.coef);
+        L.Q = ar.alloc<double>(Q.size());
+        WB_HIP(hipMemcpy(L.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
+        launch_coarsen_h(st, F.N, n, L.Q, F.coef, L.coef);
       }
     }
     L.dinv = ar.alloc<double>(L.len);
@@ -323,29 +350,7 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     if (li > 0) make_transfer(ar, L.N, L.k, H.L[li - 1].N, H.L[li - 1].k, H.L[li - 1].P, H.L[li - 1].R);
   }
   // Chebyshev bounds from the Lanczos estimate on every smoothed level
-  for (int li = 0; li + 1 < nl; ++li) {
-    Level<double>& L = H.L[li];
-    std::vector<double> b0;
-    splitmix_vector((unsigned long long)(seed_base + li), L.len, b0);
-    const int M = L.k * L.N + 1;
-    if (L.dir) {
-      for (size_t i = 0; i < L.len; ++i) {
-        const size_t g = i % L.nn;
-        const int gi = (int)(g % M), gj = (int)((g / M) % M), gl = (int)(g / ((size_t)M * M));
-        if (gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1 || gl == 0 || gl == M - 1) b0[i] = 0.0;
-      }
-    } else {
-      double mean = 0.0;
-      for (double v : b0) mean += v;
-      mean /= (double)b0.size();
-      for (double& v : b0) v -= mean;
-    }
-    auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out, s.opwork); };
-    const double lam = lanczos_max(s, op, L.len, L.dinv, b0, s.o.lanczos_steps, L.x, L.b, L.r, L.d);
-    L.lmin = 0.1 * lam;
-    L.lmax = 1.1 * lam;
-    for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
-  }
+  for (int li = 0; li + 1 < nl; ++li) set_cheb_bounds(s, H.L[li], (unsigned long long)(seed_base + li));
   // coarsest: dense inverse (velocity: interior DOFs, SPD) or pseudo-inverse (Poisson, Neumann)
   Level<double>& C = H.L[nl - 1];
   const int M = C.k * C.N + 1;
@@ -471,6 +476,32 @@ inline int mf_flag(const Solver& s) {
   return 0;
 }
 
+// Learned correction at the velocity level lc (after the plain cycle there): r = b - A x,
+// delta = rho N(feat, r / rho) / diag(A), x += alpha delta with the residual-minimizing
+// alpha clipped to [0, 2] (alpha = 0 leaves the plain V-cycle result).  Device-side only.
+template <typename T>
+void learned_delta(Solver& s, Level<T>& L, const T* r, T* delta, T* Ad) {
+  Learned& G = *s.learned;
+  hipStream_t st = s.st;
+  double* sumsq = s.red_out + 8;
+  launch_dot<T>(st, L.len, r, r, s.red_partial, sumsq);
+  launch_net_input<T>(st, G.M, 1, G.feat, r, sumsq, G.xin);
+  net_forward(st, G.params, G.xin, G.w1);
+  launch_net_delta<T>(st, G.M, G.w1.z[3], L.dinv, sumsq, delta);
+  level_op<T>(st, L, delta, Ad, s.opwork, mf_flag<T>(s));
+  launch_dot<T>(st, L.len, r, Ad, s.red_partial, s.red_out + 9);
+  launch_dot<T>(st, L.len, Ad, Ad, s.red_partial, s.red_out + 10);
+}
+
+template <typename T>
+void learned_step(Solver& s, Level<T>& L, const T* b, T* x) {
+  hipStream_t st = s.st;
+  level_op<T>(st, L, x, L.t, s.opwork, mf_flag<T>(s));
+  launch_sub<T>(st, L.len, b, L.t, L.r);
+  learned_delta<T>(s, L, L.r, L.d, L.t);
+  launch_net_guarded_update<T>(st, L.len, s.red_out + 9, x, L.d, s.learned->counters);
+}
+
 template <typename T>
 void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
   hipStream_t st = s.st;
@@ -490,6 +521,9 @@ void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
   vcycle<T>(s, H, li + 1, C.b, C.x);
   launch_kron<T>(st, L.P, L.NC, L.dir, true, C.x, x);
   chebyshev<T>(st, op, L.len, L.dinv, L.lmin, L.lmax, deg, b, x, false, L.r, L.d, L.t);
+  if (L.NC == 3 && s.learned && li == s.learned->lc && s.learned->trained && s.learned->active &&
+      s.o.use_learned)
+    learned_step<T>(s, L, b, x);
 }
 
 template <typename T>
@@ -558,7 +592,9 @@ void apply_precond(Solver& s, Precond<T>& P, const T* ru, const T* rp, T* zu, T*
   hipStream_t st = s.st;
   const Mesh& m = s.m;
   const size_t vl = (size_t)3 * m.nn;
+  // P = [[A~, B^T], [0, sign S~]] (eq. 3): zp = sign S~^-1 rp, zu = A~^-1 (ru - B^T zp)
   apply_wbfbt<T>(s, P, rp, zp);
+  if (s.o.schur_sign < 0) launch_scal<T>(st, (size_t)m.E * m.np, T(-1), zp, zp);
   launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.v1, nullptr, zp, nullptr, nullptr, false,
                s.opwork);
   launch_sub<T>(st, vl, ru, P.v1, P.v2);
@@ -605,6 +641,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
              "bad solver options");
   WB_REQUIRE(o.a_l >= 1.0 && o.a_r >= 1.0, WB_EINVAL, "boundary amplification must be >= 1");
   WB_REQUIRE(o.p_schedule == 0 || o.p_schedule == 1, WB_EINVAL, "p_schedule must be 0 or 1");
+  WB_REQUIRE(o.schur_sign == 1 || o.schur_sign == -1, WB_EINVAL, "schur_sign must be 1 or -1");
   WB_REQUIRE(o.precond_prec >= WB_FP64 && o.precond_prec <= WB_BF16X1, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
@@ -615,7 +652,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.st = st;
   Arena& ar = s.arena;
   s.red_partial = ar.alloc<double>(RED_BLOCKS * 128);
-  s.red_out = ar.alloc<double>(8);
+  s.red_out = ar.alloc<double>(16);
   const int n3 = (m.k + 1) * (m.k + 1) * (m.k + 1);
   {
     size_t wbytes = op_workspace_bytes(3, m.N, m.k, sizeof(double));
@@ -631,6 +668,26 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.pd.reset(new Precond<double>());
   Precond<double>& P = *s.pd;
   build_hierarchy(s, P.A, 3, s.mu_q, 1000);
+  // learned coarse correction: velocity level Q1 on N/2 (if it is a smoothed level)
+  for (int li = 0; li + 1 < (int)P.A.L.size(); ++li)
+    if (P.A.L[li].k == 1 && 2 * P.A.L[li].N == m.N) {
+      std::unique_ptr<Learned> G(new Learned());
+      G->lc = li;
+      G->M = P.A.L[li].N + 1;
+      const size_t M3 = (size_t)G->M * G->M * G->M;
+      G->params = ar.alloc<float>(net_param_count());
+      launch_fill<float>(st, G->params, 0.f, net_param_count());
+      G->feat = ar.alloc<float>(M3);
+      G->xin = ar.alloc<float>(4 * M3);
+      G->elem_tmp = ar.alloc<float>((size_t)P.A.L[li].E);
+      net_work_carve(G->w1, G->M, 1, ar.raw(net_work_bytes(G->M, 1)));
+      G->counters = ar.alloc<int>(2);
+      launch_node_feature(st, P.A.L[li].N, P.A.L[li].coef, G->feat, G->elem_tmp);
+      s.learned = std::move(G);
+      break;
+    }
+  WB_REQUIRE(!o.use_learned || s.learned, WB_EUNSUPPORTED,
+             "learned correction needs a velocity level Q1 on N/2 above the coarsest");
   // weights C = M(a_l sqrt(mu)), D = M(a_r sqrt(mu)) (eq. 8, Sec. 5); stored inverted
   const double amps[2] = {o.a_l, o.a_r};
   auto bh = make_bhat(m.k);
@@ -721,6 +778,7 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
     WB_HIP(hipMemcpyAsync(s.w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     double beta = bnorm;
     std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), hh(2 * (R + 2) + 1);
+    std::vector<double> hist;
     bool done = false;
     while (!done) {
       std::fill(H.begin(), H.end(), 0.0);
@@ -764,6 +822,20 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
         ++it;
         jdone = j + 1;
         if (s.o.verbose) fprintf(stderr, "fgmres %4d  %.3e\n", it, std::fabs(g[j + 1]) / bnorm);
+        // stagnation with the learned correction: less than a halving of the residual over the
+        // last 20 iterations switches it off for the rest of the solve (flexible GMRES allows
+        // the preconditioner to change between iterations)
+        hist.push_back(std::fabs(g[j + 1]));
+        if (s.learned && s.learned->active && s.learned->trained && s.o.use_learned &&
+            hist.size() > 20 && hist.back() > 0.5 * hist[hist.size() - 21]) {
+          s.learned->active = false;
+          s.fell_back += 1;
+          if (s.pgraph) {
+            WB_HIP(hipStreamSynchronize(st));
+            (void)hipGraphExecDestroy(s.pgraph);
+            s.pgraph = nullptr;
+          }
+        }
         if (std::fabs(g[j + 1]) <= rtol * bnorm || it >= max_iter || nrm == 0.0) break;
       }
       std::vector<double> y(jdone);
@@ -836,6 +908,17 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
   const Mesh& m = s.m;
   const size_t n = s.n_tot, vl = (size_t)3 * m.nn, pl = (size_t)m.E * m.np;
   s.learned_used = s.fell_back = 0;
+  if (s.learned) {
+    launch_fill<int>(st, s.learned->counters, 0, 2);
+    if (!s.learned->active) {
+      s.learned->active = true;
+      if (s.pgraph) {
+        WB_HIP(hipStreamSynchronize(st));
+        (void)hipGraphExecDestroy(s.pgraph);
+        s.pgraph = nullptr;
+      }
+    }
+  }
   // b = [f with zero boundary entries; 0]
   WB_HIP(hipMemcpyAsync(s.bvec, f, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
   launch_mask_boundary<double>(st, m.M, 3, s.bvec);
@@ -853,7 +936,12 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
   launch_remove_mean<double>(st, m.E, m.np, s.xvec + vl, s.red_partial, s.red_out + 3);
   WB_HIP(hipMemcpyAsync(u, s.xvec, sizeof(double) * vl, hipMemcpyDeviceToDevice, st));
   WB_HIP(hipMemcpyAsync(p, s.xvec + vl, sizeof(double) * pl, hipMemcpyDeviceToDevice, st));
+  int cnt[2] = {0, 0};
+  if (s.learned) WB_HIP(hipMemcpyAsync(cnt, s.learned->counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
   WB_HIP(hipStreamSynchronize(st));
+  // accepted correction steps; rejected ones (alpha = 0) plus a stagnation switch-off
+  s.learned_used = cnt[0];
+  s.fell_back += cnt[1];
   if (rep) {
     rep->iters = it;
     rep->rel_res = relres;
@@ -911,6 +999,225 @@ wb_status subsolve(Solver& s, int which, const double* b_in, double* x, wb_repor
     rep->device_bytes = s.arena.bytes();
   }
   return status;
+}
+
+// ------------------------------------------------------------------ learned correction
+namespace {
+void drop_graph(Solver& s) {
+  if (s.pgraph) {
+    WB_HIP(hipStreamSynchronize(s.st));
+    (void)hipGraphExecDestroy(s.pgraph);
+    s.pgraph = nullptr;
+  }
+}
+
+// coefficient of level `to` from level `to - 1` with the hierarchy's coarsening matrices
+void coarsen_level(hipStream_t st, const Level<double>& F, const Level<double>& L, const double* fc,
+                   double* lc) {
+  if (F.N == L.N) launch_coarsen_p(st, L.E, F.k + 1, L.k + 1, L.Q, fc, lc);
+  else launch_coarsen_h(st, F.N, L.k + 1, L.Q, fc, lc);
+}
+}  // namespace
+
+void learned_set(Solver& s, const float* params_host) {
+  WB_REQUIRE(s.learned, WB_EUNSUPPORTED, "no learned level (Q1 on N/2) on this mesh");
+  WB_HIP(hipMemcpyAsync(s.learned->params, params_host, sizeof(float) * net_param_count(),
+                        hipMemcpyHostToDevice, s.st));
+  WB_HIP(hipStreamSynchronize(s.st));
+  s.learned->trained = true;
+  drop_graph(s);
+}
+
+void learned_probe(Solver& s, const double* r, double* delta, double* alpha_host) {
+  WB_REQUIRE(s.learned, WB_EUNSUPPORTED, "no learned level (Q1 on N/2) on this mesh");
+  Learned& G = *s.learned;
+  Level<double>& L = s.pd->A.L[G.lc];
+  learned_delta<double>(s, L, r, delta, L.t);
+  launch_fill<double>(s.st, L.x, 0.0, L.len);
+  launch_net_guarded_update<double>(s.st, L.len, s.red_out + 9, L.x, delta, G.counters);
+  WB_HIP(hipMemcpyAsync(alpha_host, s.red_out + 11, sizeof(double), hipMemcpyDeviceToHost, s.st));
+  WB_HIP(hipStreamSynchronize(s.st));
+}
+
+void learned_train(Solver& s, int n_fields, const int* n_sinkers, const double* centers,
+                   const TrainOpts& o, TrainReport* rep) {
+  WB_REQUIRE(s.learned, WB_EUNSUPPORTED, "no learned level (Q1 on N/2) on this mesh");
+  WB_REQUIRE(n_fields >= 1 && n_sinkers && o.pairs_per_field >= 1 && o.vcycles >= 1 &&
+                 o.epochs >= 0 && o.batch >= 1 && o.lr > 0 && o.n_valid >= 0 &&
+                 o.n_valid < n_fields && o.mu_min > 0 && o.mu_max >= o.mu_min,
+             WB_EINVAL, "bad training options");
+  Learned& G = *s.learned;
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  Hierarchy<double>& A = s.pd->A;
+  const int lc = G.lc, M = G.M;
+  const size_t M3 = (size_t)M * M * M, len = 3 * M3;
+  const int ppf = o.pairs_per_field;
+  const int nt = n_fields * ppf, nv = o.n_valid * ppf, ntr = nt - nv;
+  const int B = std::min(o.batch, ntr);
+  int max_ns = 0;
+  for (int f = 0; f < n_fields; ++f) {
+    WB_REQUIRE(n_sinkers[f] >= 0, WB_EINVAL, "negative sinker count");
+    max_ns = std::max(max_ns, n_sinkers[f]);
+  }
+  WB_REQUIRE(max_ns == 0 || centers, WB_EINVAL, "NULL centers");
+  Arena ar;  // training buffers, freed on return
+  struct StreamDrain {  // destroyed before `ar`: queued work ends before the buffers are freed
+    hipStream_t st;
+    ~StreamDrain() { (void)hipStreamSynchronize(st); }
+  } drain{st};
+  // Training hierarchy: the solver's levels lc .. coarsest (shapes, transfers, coarsening
+  // matrices) with each field's own coefficients, diagonals and Chebyshev bounds; the coarsest
+  // direct solve is the solver's own factorization.
+  Hierarchy<double> T;
+  T.L.resize(A.L.size() - lc);
+  for (size_t j = 0; j < T.L.size(); ++j) {
+    Level<double>& L = T.L[j];
+    L = A.L[lc + j];
+    const int n = L.k + 1;
+    L.coef = ar.alloc<double>((size_t)L.E * n * n * n);
+    L.dinv = ar.alloc<double>(L.len);
+    for (double** v : {&L.x, &L.b, &L.r, &L.d, &L.t}) *v = ar.alloc<double>(L.len);
+  }
+  T.nd = A.nd;
+  T.G = A.G;
+  T.gidx = A.gidx;
+  std::vector<double*> chain(lc + 1, nullptr);
+  for (int li = 0; li < lc; ++li) {
+    const int n = A.L[li].k + 1;
+    chain[li] = ar.alloc<double>((size_t)A.L[li].E * n * n * n);
+  }
+  chain[lc] = T.L[0].coef;
+  double* dcent = ar.alloc<double>(3 * (size_t)std::max(1, max_ns));
+  float* X = ar.alloc<float>((size_t)nt * 4 * M3);
+  float* Tt = ar.alloc<float>((size_t)nt * 3 * M3);
+  float* Wt = ar.alloc<float>((size_t)nt * 3 * M3);
+  float* feat = ar.alloc<float>(M3);
+  float* etmp = ar.alloc<float>((size_t)T.L[0].E);
+  double* e = ar.alloc<double>(len);
+  double* bb = ar.alloc<double>(len);
+  double* rr = ar.alloc<double>(len);
+  double* sums = ar.alloc<double>(4);
+  const bool was_active = G.active;
+  G.active = false;
+  drop_graph(s);
+  const double t0 = now_s();
+  size_t coff = 0;
+  for (int f = 0; f < n_fields; ++f) {
+    const int ns = n_sinkers[f];
+    if (ns > 0)
+      WB_HIP(hipMemcpyAsync(dcent, centers + coff, sizeof(double) * 3 * ns, hipMemcpyHostToDevice, st));
+    coff += 3 * (size_t)ns;
+    launch_sinker_q(st, m.N, m.k, dcent, ns, o.delta, o.omega, o.mu_min, o.mu_max, 0.0, chain[0],
+                    nullptr);
+    for (int li = 1; li <= lc; ++li) coarsen_level(st, A.L[li - 1], A.L[li], chain[li - 1], chain[li]);
+    for (size_t j = 0; j < T.L.size(); ++j) {
+      Level<double>& L = T.L[j];
+      if (j > 0) coarsen_level(st, T.L[j - 1], L, T.L[j - 1].coef, L.coef);
+      launch_fill<double>(st, L.dinv, 0.0, L.len);
+      launch_diag(st, 3, L.N, L.k, true, L.coef, L.dinv);
+      launch_invert_diag(st, 3, L.N, L.k, true, L.dinv);
+      for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
+    }
+    for (size_t j = 0; j + 1 < T.L.size(); ++j)
+      set_cheb_bounds(s, T.L[j], (unsigned long long)(1000 + lc + j));
+    launch_node_feature(st, T.L[0].N, T.L[0].coef, feat, etmp);
+    Level<double>& L0 = T.L[0];
+    for (int j = 0; j < ppf; ++j) {
+      const int pid = f * ppf + j;
+      launch_splitmix_field(st, M, o.seed + (unsigned long long)pid, e);
+      for (int v = 0; v < o.vcycles; ++v) {  // e <- (I - V A) e
+        level_op<double>(st, L0, e, bb, s.opwork);
+        vcycle<double>(s, T, 0, bb, rr);
+        launch_axpby<double>(st, len, -1.0, rr, 1.0, e);
+      }
+      level_op<double>(st, L0, e, rr, s.opwork);  // r = A e
+      launch_dot<double>(st, len, rr, rr, s.red_partial, sums);
+      launch_energy_diag(st, M, e, L0.dinv, s.red_partial, sums + 1);
+      launch_net_pair(st, M, feat, e, rr, L0.dinv, sums, X + (size_t)pid * 4 * M3,
+                      Tt + (size_t)pid * 3 * M3, Wt + (size_t)pid * 3 * M3);
+    }
+  }
+  WB_HIP(hipStreamSynchronize(st));
+  const double t1 = now_s();
+  // Adam on the training pairs (the trailing n_valid fields are held out)
+  const size_t np = net_param_count();
+  NetWork W;
+  net_work_carve(W, M, B, ar.raw(net_work_bytes(M, B)));
+  float* grad = ar.alloc<float>(np);
+  float* am = ar.alloc<float>(np);
+  float* av = ar.alloc<float>(np);
+  launch_fill<float>(st, am, 0.f, np);
+  launch_fill<float>(st, av, 0.f, np);
+  float* bx = ar.alloc<float>((size_t)B * 4 * M3);
+  float* bt = ar.alloc<float>((size_t)B * 3 * M3);
+  float* bw = ar.alloc<float>((size_t)B * 3 * M3);
+  const int nb = ntr / B;
+  double* losses = ar.alloc<double>((size_t)std::max(nb, 1));
+  net_init(st, G.params, o.seed ^ 0x5EEDULL);
+  std::vector<int> perm(ntr);
+  for (int i = 0; i < ntr; ++i) perm[i] = i;
+  std::vector<double> lh(std::max(nb, 1));
+  int step = 0;
+  double first = 0.0, last = 0.0;
+  for (int ep = 0; ep < o.epochs; ++ep) {
+    std::vector<double> u;
+    splitmix_vector(o.seed + 7919ULL * (ep + 1), (size_t)ntr, u);
+    for (int i = ntr - 1; i > 0; --i) {  // Fisher-Yates with u in [-1, 1)
+      const int jj = std::min(i, (int)((0.5 * (u[i] + 1.0)) * (i + 1)));
+      std::swap(perm[i], perm[jj]);
+    }
+    for (int bi = 0; bi < nb; ++bi) {
+      for (int j = 0; j < B; ++j) {
+        const size_t q = (size_t)perm[bi * B + j];
+        WB_HIP(hipMemcpyAsync(bx + (size_t)j * 4 * M3, X + q * 4 * M3, sizeof(float) * 4 * M3,
+                              hipMemcpyDeviceToDevice, st));
+        WB_HIP(hipMemcpyAsync(bt + (size_t)j * 3 * M3, Tt + q * 3 * M3, sizeof(float) * 3 * M3,
+                              hipMemcpyDeviceToDevice, st));
+        WB_HIP(hipMemcpyAsync(bw + (size_t)j * 3 * M3, Wt + q * 3 * M3, sizeof(float) * 3 * M3,
+                              hipMemcpyDeviceToDevice, st));
+      }
+      net_forward(st, G.params, bx, W);
+      net_backward(st, G.params, bx, bt, bw, W, grad, losses + bi);
+      net_adam(st, np, G.params, grad, am, av, ++step, (float)o.lr);
+    }
+    WB_HIP(hipMemcpyAsync(lh.data(), losses, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    WB_HIP(hipStreamSynchronize(st));
+    double mean = 0.0;
+    for (int bi = 0; bi < nb; ++bi) mean += lh[bi];
+    mean /= std::max(nb, 1);
+    if (ep == 0) first = mean;
+    last = mean;
+    if (s.o.verbose) fprintf(stderr, "learned epoch %3d  loss %.4e\n", ep, mean);
+  }
+  // validation loss on the held-out fields (batch 1)
+  double vloss = 0.0;
+  if (nv > 0) {
+    NetWork V1;
+    net_work_carve(V1, M, 1, ar.raw(net_work_bytes(M, 1)));
+    std::vector<double> vl(nv);
+    double* vd = ar.alloc<double>(nv);
+    for (int i = 0; i < nv; ++i) {
+      const size_t q = (size_t)(ntr + i);
+      net_forward(st, G.params, X + q * 4 * M3, V1);
+      net_backward(st, G.params, X + q * 4 * M3, Tt + q * 3 * M3, Wt + q * 3 * M3, V1, grad, vd + i);
+    }
+    WB_HIP(hipMemcpyAsync(vl.data(), vd, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+    WB_HIP(hipStreamSynchronize(st));
+    for (double v : vl) vloss += v / nv;
+  }
+  WB_HIP(hipStreamSynchronize(st));
+  G.trained = true;
+  G.active = was_active;
+  if (rep) {
+    rep->loss_first = first;
+    rep->loss_last = last;
+    rep->valid_loss = vloss;
+    rep->t_pairs_s = t1 - t0;
+    rep->t_train_s = now_s() - t1;
+    rep->n_params = (long long)np;
+    rep->n_pairs = nt;
+  }
 }
 
 }  // namespace wb

@@ -30,7 +30,8 @@ class wb_opts(ctypes.Structure):
                 ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("precond_prec", ctypes.c_int),
                 ("use_learned", ctypes.c_int), ("p_schedule", ctypes.c_int),
-                ("verbose", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("schur_sign", ctypes.c_int)]
 
 
 class wb_report(ctypes.Structure):
@@ -38,6 +39,21 @@ class wb_report(ctypes.Structure):
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
                 ("fell_back", ctypes.c_int), ("learned_used", ctypes.c_int),
                 ("device_bytes", ctypes.c_size_t)]
+
+
+class wb_train_opts(ctypes.Structure):
+    _fields_ = [("pairs_per_field", ctypes.c_int), ("vcycles", ctypes.c_int),
+                ("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_ulonglong), ("delta", ctypes.c_double),
+                ("omega", ctypes.c_double), ("mu_min", ctypes.c_double),
+                ("mu_max", ctypes.c_double), ("n_valid", ctypes.c_int)]
+
+
+class wb_train_report(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("valid_loss", ctypes.c_double), ("t_pairs_s", ctypes.c_double),
+                ("t_train_s", ctypes.c_double), ("n_params", ctypes.c_longlong),
+                ("n_pairs", ctypes.c_int)]
 
 
 _lib = None
@@ -74,9 +90,17 @@ SIGNATURES = {
     "wb_solver_query": (I, [VP, I, I, VP, VP]),
     "wb_solver_levels": (I, [VP, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                              ctypes.POINTER(D)]),
-    "wb_learned_train": (I, [VP, VP, VP, I, I, I, D, ctypes.POINTER(D), VP]),
+    "wb_train_opts_default": (None, [ctypes.POINTER(wb_train_opts)]),
+    "wb_learned_train": (I, [VP, I, VP, VP, ctypes.POINTER(wb_train_opts),
+                             ctypes.POINTER(wb_train_report), VP]),
     "wb_learned_get": (I, [VP, VP, ctypes.POINTER(LL)]),
     "wb_learned_set": (I, [VP, VP, LL]),
+    "wb_learned_info": (I, [VP, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(LL)]),
+    "wb_learned_probe": (I, [VP, VP, VP, ctypes.POINTER(D), VP]),
+    "wb_net_param_count": (LL, []),
+    "wb_net_eval": (I, [I, I, VP, VP, VP, VP, VP, VP, ctypes.POINTER(D), VP]),
+    "wb_net_adam": (I, [LL, VP, VP, VP, VP, I, D, VP]),
+    "wb_net_feature": (I, [I, VP, VP, VP]),
     "wb_profile_enable": (None, [I]),
     "wb_profile_summary": (LL, [ctypes.c_char_p, LL, I]),
 }
@@ -324,3 +348,66 @@ class Solver:
         lm = (D * 16)()
         _check(lib().wb_solver_levels(self.h, which, ctypes.byref(nl), Ns, ks, lm))
         return [(Ns[i], ks[i], lm[i]) for i in range(nl.value)]
+
+    # ---- learned coarse correction
+    def learned_info(self):
+        lv, M, n = I(), I(), LL()
+        _check(lib().wb_learned_info(self.h, ctypes.byref(lv), ctypes.byref(M), ctypes.byref(n)))
+        return lv.value, M.value, n.value
+
+    def learned_train(self, centers_per_field, stream=None, **kw):
+        """centers_per_field: list of [n_i][3] arrays (one per seeded field)."""
+        o = wb_train_opts()
+        lib().wb_train_opts_default(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        ns = np.array([len(c) for c in centers_per_field], dtype=np.int32)
+        flat = (np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1, 3)
+                                                     for c in centers_per_field]))
+                if ns.sum() > 0 else np.zeros((1, 3)))
+        rep = wb_train_report()
+        _check(lib().wb_learned_train(self.h, len(ns), ns.ctypes.data_as(VP),
+                                      flat.ctypes.data_as(VP), ctypes.byref(o), ctypes.byref(rep),
+                                      _stream(stream)))
+        return rep
+
+    def learned_get(self):
+        n = LL()
+        _check(lib().wb_learned_get(self.h, None, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.float32)
+        _check(lib().wb_learned_get(self.h, out.ctypes.data_as(VP), ctypes.byref(n)))
+        return out
+
+    def learned_set(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().wb_learned_set(self.h, p.ctypes.data_as(VP), p.size))
+
+    def learned_probe(self, r, delta, stream=None):
+        import torch
+        a = D()
+        _check(lib().wb_learned_probe(self.h, _ptr(r, torch.float64), _ptr(delta, torch.float64),
+                                      ctypes.byref(a), _stream(stream)))
+        return a.value
+
+
+def wb_net_eval(M, B, params, x, out, t=None, w=None, grad=None, stream=None):
+    """Network forward (and loss + gradient when t, w, grad are given); returns the loss."""
+    import torch
+    f32 = torch.float32
+    loss = D()
+    _check(lib().wb_net_eval(M, B, _ptr(params, f32), _ptr(x, f32), _ptr(t, f32), _ptr(w, f32),
+                             _ptr(out, f32), _ptr(grad, f32), ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def wb_net_adam(params, grad, m, v, step, lr, stream=None):
+    import torch
+    f32 = torch.float32
+    _check(lib().wb_net_adam(params.numel(), _ptr(params, f32), _ptr(grad, f32), _ptr(m, f32),
+                             _ptr(v, f32), step, lr, _stream(stream)))
+
+
+def wb_net_feature(N, coef, feat, stream=None):
+    import torch
+    _check(lib().wb_net_feature(N, _ptr(coef, torch.float64), _ptr(feat, torch.float32),
+                                _stream(stream)))

@@ -218,3 +218,35 @@ def test_bf16_mfma_preconditioner_reaches_tolerance(name, form):
         assert rb.iters <= r64.iters + 3
     else:
         assert rb.iters <= 2 * r64.iters + 5
+
+
+def test_schur_sign_both_readings_match_oracle():
+    """Both readings of the Schur block of eq. (3): -S~ (default) and +S~ as printed; the GPU
+    preconditioner and FGMRES iteration counts follow the oracle for each, and -S~ needs fewer
+    iterations."""
+    wb = _wb()
+    w, st, P, m, v, s = _pair("n8k2")
+    om = st.mesh
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    its = {}
+    for sign in (-1, 1):
+        Po = P if sign == -1 else solver.Preconditioner(st, schur_sign=1)
+        sg = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, schur_sign=sign)
+        ru = random_vector(41, om.u_dof)
+        ru[om.vel_boundary] = 0.0
+        rp = st.remove_mean(random_vector(42, om.p_dof))
+        zu = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+        zp = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+        sg.precond(dev(ru), dev(rp), zu, zp)
+        ref = Po.apply(np.concatenate([ru[st.idx], rp]))
+        assert _rel(host(zu), st.embed_u(ref[:st.nu])) < 1e-9
+        assert _rel(host(zp), ref[st.nu:]) < 1e-9
+        u = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+        p = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+        rep = sg.solve(f, u, p)
+        _, it_o, _ = solver.fgmres(st.stokes_matvec, b, Po.apply, rtol=1e-6)
+        assert abs(rep.iters - it_o) <= 2, (sign, rep.iters, it_o)
+        its[sign] = rep.iters
+    assert its[-1] < its[1], its
