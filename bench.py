@@ -134,8 +134,8 @@ def main():
                      "share": round(ms / step_total, 4)}
                     for k, (n, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])[:6]]
 
-    # the A(mu) apply at the finest level: 100 back-to-back accumulating applies, each
-    # bracketed by HIP events on the stream it is launched on
+    # the A(mu) apply y = A u at the finest level: 100 back-to-back applies, each bracketed by
+    # HIP events on the stream it is launched on
     a_apply = measure_a_apply(wb, torch, mesh, w, centers)
     log(f"[bench] A apply {w.name}: {a_apply['avg_ms'] * 1e3:.1f} us, {a_apply['gdofs']} GDoF/s")
     a_big = None
@@ -195,12 +195,12 @@ def measure_a_apply(wb, torch, mesh, w, centers, reps=100):
     x = torch.rand(mesh.u_len, dtype=torch.float64, device="cuda")
     y = torch.zeros(mesh.u_len, dtype=torch.float64, device="cuda")
     for _ in range(10):
-        wb.wb_apply_A_add(mesh, v, x, y)
+        wb.wb_apply_A(mesh, v, x, y)
     torch.cuda.synchronize()
     wb.wb_profile_enable(True)
     wb.wb_profile_summary(reset=True)
     for _ in range(reps):
-        wb.wb_apply_A_add(mesh, v, x, y)
+        wb.wb_apply_A(mesh, v, x, y)
     torch.cuda.synchronize()
     wb.wb_profile_enable(False)
     aprof = wb.wb_profile_summary(reset=True)
@@ -218,6 +218,7 @@ def measure_a_apply(wb, torch, mesh, w, centers, reps=100):
             "algorithmic_GBs": round(a_bytes / (a_avg * 1e-3) / 1e9, 1),
             "hbm_frac": round(a_bytes / (a_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "bytes_per_launch": a_bytes,
+            "traffic_bytes_per_launch": traffic_for(a_key),
             "cache_note": ("working set %.0f MB %s the 256 MB Infinity Cache"
                            % (a_bytes / 1e6, "fits in" if a_bytes < 256e6 else "exceeds"))}
 
