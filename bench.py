@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-big", action="store_true", help="skip the 64^3 Q3 A-apply measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip training the learned correction")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -158,6 +159,15 @@ def main():
                                "rel_res": rep.rel_res, "rel_err_u_vs_fp64": du,
                                "rel_err_p_vs_fp64": dp}
         log(f"[bench] mixed: setup {ts:.3f}s solve {tv:.3f}s iters {rep.iters} du {du:.1e} dp {dp:.1e}")
+        rep, ts, tv = step(wb.WB_BF16)
+        du = (torch.linalg.norm(u - u64) / torch.linalg.norm(u64)).item()
+        dp = (torch.linalg.norm(p - p64) / torch.linalg.norm(p64)).item()
+        forms["mixed_bf16x3_mfma"] = {"setup_s": round(ts, 4), "solve_s": round(tv, 4),
+                                      "iters": rep.iters, "rel_res": rep.rel_res,
+                                      "rel_err_u_vs_fp64": du, "rel_err_p_vs_fp64": dp}
+        log(f"[bench] bf16x3: setup {ts:.3f}s solve {tv:.3f}s iters {rep.iters} du {du:.1e} dp {dp:.1e}")
+    if not args.no_learned:
+        forms["learned"] = learned_form(wb, torch, mesh, w, centers, f, u64, p64)
 
     cpu = None
     if not args.no_cpu:
@@ -221,6 +231,38 @@ def measure_a_apply(wb, torch, mesh, w, centers, reps=100):
             "traffic_bytes_per_launch": traffic_for(a_key),
             "cache_note": ("working set %.0f MB %s the 256 MB Infinity Cache"
                            % (a_bytes / 1e6, "fits in" if a_bytes < 256e6 else "exceeds"))}
+
+
+def learned_form(wb, torch, mesh, w, centers, f, u64, p64, n_fields=250, pairs=8, epochs=20):
+    """Train the learned coarse correction on seeded fields 1000.. (not the evaluation field),
+    then solve with it; reported next to the plain FP64 solve (same preconditioner otherwise)."""
+    from synthetic import sinker_centers
+    v = wb.Viscosity.sinker(mesh, centers, w.delta, w.omega, w.mu_min, w.mu_max)
+    s = wb.Solver(mesh, v, a_l=w.a_l, a_r=w.a_r, use_learned=1)
+    fields = [sinker_centers(1000 + i, w.n_sinkers) for i in range(n_fields)]
+    tr = s.learned_train(fields, pairs_per_field=pairs, epochs=epochs, batch=8, lr=1e-3,
+                         n_valid=n_fields // 10, delta=w.delta, omega=w.omega, mu_min=w.mu_min,
+                         mu_max=w.mu_max)
+    u = torch.empty_like(u64)
+    p = torch.empty_like(p64)
+    s.solve(f, u, p, allow_noconv=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = s.solve(f, u, p, allow_noconv=True)
+    torch.cuda.synchronize()
+    tv = time.perf_counter() - t0
+    du = (torch.linalg.norm(u - u64) / torch.linalg.norm(u64)).item()
+    out = {"solve_s": round(tv, 4), "iters": rep.iters, "rel_res": rep.rel_res,
+           "accepted_steps": rep.learned_used, "rejected_or_switched": rep.fell_back,
+           "rel_err_u_vs_fp64": du,
+           "training": {"fields": n_fields, "pairs": tr.n_pairs, "epochs": epochs,
+                        "loss_first_epoch": round(tr.loss_first, 4),
+                        "loss_last_epoch": round(tr.loss_last, 4),
+                        "valid_loss": round(tr.valid_loss, 4),
+                        "pairs_s": round(tr.t_pairs_s, 2), "adam_s": round(tr.t_train_s, 2)}}
+    log(f"[bench] learned: {rep.iters} its {tv:.3f}s, loss {tr.loss_first:.3f} -> {tr.loss_last:.3f}")
+    del s, v
+    return out
 
 
 def kernel_source_hash():
