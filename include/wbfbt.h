@@ -269,6 +269,12 @@ WB_API wb_status wb_net_adam(long long n, float* params, const float* grad, floa
                              int step, double lr, void* stream);
 WB_API wb_status wb_net_feature(int N, const double* coef, float* feat, void* stream);
 
+/* ---- device memory ----
+ * Device memory of destroyed solvers is kept in a cache of blocks by (device, size) and reused
+ * by later solvers that ask for the same sizes; a failed allocation empties the cache and
+ * retries.  wb_mem_trim frees every cached block (call it with no solver work in flight). */
+WB_API void wb_mem_trim(void);
+
 /* ---- instrumentation ----
  * When enabled, every operator-kernel launch is bracketed by HIP events on the
  * stream it is launched on.  wb_profile_summary writes lines

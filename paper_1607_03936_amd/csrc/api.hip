@@ -580,6 +580,8 @@ wb_status wb_learned_probe(wb_solver* sh, const double* r, double* delta, double
   });
 }
 
+void wb_mem_trim(void) { mem_trim(); }
+
 long long wb_net_param_count(void) { return (long long)net_param_count(); }
 
 wb_status wb_net_eval(int M, int B, const float* params, const float* x, const float* t,

@@ -107,6 +107,20 @@ template <typename T> void launch_mul(hipStream_t st, size_t n, const T* a, cons
 // r = b - t
 template <typename T> void launch_sub(hipStream_t st, size_t n, const T* b, const T* t, T* r);
 
+// Jacobi-CG step halves with the scalars in device memory: r -= (rz/pq) q, z = dinv r; and
+// p = z + (rz_new/rz_old) p (non-positive denominators give a zero coefficient).
+void launch_cg_r(hipStream_t st, size_t n, const double* q, const double* dinv, double* r, double* z,
+                 const double* rz, const double* pq);
+void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const double* rz_new,
+                 const double* rz_old);
+// x_i = 2 U(splitmix64(seed * 2^32 + i)) - 1, zero on boundary nodes of an [NC][M^3] vector
+// when M > 0 (the counter-based generator of the eigenvalue-estimate start vectors).
+void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int M, double* x);
+// x -= mean(x) (two-stage sum, deterministic)
+void launch_remove_global_mean(hipStream_t st, size_t n, double* x, double* partial, double* scratch);
+// x = e_j (unit vector of length n)
+void launch_unit(hipStream_t st, size_t n, size_t j, double* x);
+
 // Reductions into a device FP64 scalar (two stages, deterministic).
 template <typename T>
 void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partial, double* out);

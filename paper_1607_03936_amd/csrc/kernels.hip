@@ -1310,6 +1310,61 @@ __global__ void k_gemv(size_t n, int nv, const double* __restrict__ V, size_t ld
   w[i] += sign * s;
 }
 
+// Jacobi-CG steps with device scalars (eigenvalue estimate): alpha = rz / pq, r -= alpha q,
+// z = dinv r; then beta = rz_new / rz, p = z + beta p.  Non-positive denominators give 0 (the
+// host reads the scalars afterwards and stops the recurrence there).
+__global__ void k_cg_r(size_t n, const double* __restrict__ q, const double* __restrict__ dinv,
+                       double* __restrict__ r, double* __restrict__ z, const double* __restrict__ rz,
+                       const double* __restrict__ pq) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = (*pq > 0.0 && *rz > 0.0) ? *rz / *pq : 0.0;
+  const double ri = r[i] - a * q[i];
+  r[i] = ri;
+  z[i] = dinv[i] * ri;
+}
+__global__ void k_cg_p(size_t n, const double* __restrict__ z, double* __restrict__ p,
+                       const double* __restrict__ rz_new, const double* __restrict__ rz_old) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double b = *rz_old > 0.0 ? *rz_new / *rz_old : 0.0;
+  p[i] = z[i] + b * p[i];
+}
+// Counter-based splitmix64 uniform in [-1, 1): x_i = 2 U(mix(seed * 2^32 + i)) - 1; with
+// M > 0 the entries on boundary nodes of an [NC][M^3] nodal vector are zeroed.
+__global__ void k_splitmix_vec(size_t n, unsigned long long seed, int M, double* __restrict__ x) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = (seed << 32) + (unsigned long long)i + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  double v = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  if (M > 0) {
+    const size_t nn = (size_t)M * M * M, g = i % nn;
+    const int gi = (int)(g % M), gj = (int)((g / M) % M), gl = (int)(g / ((size_t)M * M));
+    if (gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1 || gl == 0 || gl == M - 1) v = 0.0;
+  }
+  x[i] = v;
+}
+__global__ void __launch_bounds__(256) k_sum_partial(size_t n, const double* __restrict__ x,
+                                                     double* partial) {
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    s += x[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+__global__ void k_sub_mean(size_t n, double* __restrict__ x, const double* __restrict__ sum) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] -= *sum / (double)n;
+}
+
+__global__ void k_unit(size_t n, size_t j, double* __restrict__ x) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = i == j ? 1.0 : 0.0;
+}
+
 }  // namespace
 
 // ================================================================== launchers
@@ -1573,6 +1628,28 @@ void launch_gemv_sub(hipStream_t st, size_t n, int nv, const double* V, size_t l
 void launch_gemv_add(hipStream_t st, size_t n, int nv, const double* Z, size_t ld, const double* y,
                      double* x) {
   hipLaunchKernelGGL(k_gemv, dim3(grid_for(n, 256)), dim3(256), 0, st, n, nv, Z, ld, y, 1.0, x);
+}
+
+void launch_cg_r(hipStream_t st, size_t n, const double* q, const double* dinv, double* r, double* z,
+                 const double* rz, const double* pq) {
+  hipLaunchKernelGGL(k_cg_r, dim3(grid_for(n, 256)), dim3(256), 0, st, n, q, dinv, r, z, rz, pq);
+}
+void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const double* rz_new,
+                 const double* rz_old) {
+  hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n, 256)), dim3(256), 0, st, n, z, p, rz_new, rz_old);
+}
+void launch_unit(hipStream_t st, size_t n, size_t j, double* x) {
+  hipLaunchKernelGGL(k_unit, dim3(grid_for(n, 256)), dim3(256), 0, st, n, j, x);
+}
+
+void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int M, double* x) {
+  hipLaunchKernelGGL(k_splitmix_vec, dim3(grid_for(n, 256)), dim3(256), 0, st, n, seed, M, x);
+}
+void launch_remove_global_mean(hipStream_t st, size_t n, double* x, double* partial, double* scratch) {
+  const int nb = (int)std::min<size_t>(RED_BLOCKS, grid_for(n, 256));
+  hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(256), 0, st, n, x, partial);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, st, nb, partial, scratch);
+  hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n, 256)), dim3(256), 0, st, n, x, scratch);
 }
 
 }  // namespace wb

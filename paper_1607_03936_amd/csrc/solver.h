@@ -10,9 +10,13 @@
 
 namespace wb {
 
-// Device allocations owned by one object, freed together.
+// Device allocations owned by one object, released together (into the block cache, see
+// mem_trim).  Sizes are rounded up to 256 bytes.
 class Arena {
  public:
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
   ~Arena();
   template <typename T>
   T* alloc(size_t n) {
@@ -23,8 +27,12 @@ class Arena {
 
  private:
   std::vector<void*> ptrs_;
+  std::vector<size_t> sizes_;
   size_t bytes_ = 0;
+  int dev_ = 0;
 };
+// Free every cached device block.
+void mem_trim();
 
 // One re-discretized level of a hierarchy (velocity: NC = 3, Dirichlet; Poisson: NC = 1, Neumann).
 template <typename T>
@@ -54,6 +62,7 @@ struct Hierarchy {
 std::vector<std::pair<int, int>> level_schedule(int N, int k, int p_schedule);
 
 struct Solver;
+constexpr int LZ_SLOTS = 256;
 
 // Preconditioner state in precision T (FP64 or FP32).
 template <typename T>
@@ -94,7 +103,8 @@ struct Solver {
   std::unique_ptr<Precond<float>> pf;
   void* opwork = nullptr;         // face-array workspace shared by all operator applies
   double* red_partial = nullptr;  // reduction scratch
-  double* red_out = nullptr;      // [8] device scalars
+  double* red_out = nullptr;      // [16] device scalars
+  double* lz = nullptr;           // [LZ_SLOTS] Lanczos scalars
   // Krylov space
   size_t n_tot = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hbuf = nullptr, *mpartial = nullptr;

@@ -5,22 +5,74 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "solver.h"
 
 namespace wb {
 
 // ------------------------------------------------------------------ arena
-Arena::~Arena() {
-  for (void* p : ptrs_) (void)hipFree(p);
+// Device blocks released by destroyed arenas are kept per (device, size) and handed to the next
+// request of the same size, so that creating solvers of one mesh again and again (a time step
+// loop, a benchmark) does not pay hipMalloc / hipFree each time.  An allocation failure empties
+// the cache and retries; mem_trim() empties it on request.
+namespace {
+std::mutex g_pool_mu;
+std::multimap<std::pair<int, size_t>, void*> g_pool;
+
+void pool_trim_locked() {
+  for (auto& kv : g_pool) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first.first);
+    (void)hipFree(kv.second);
+    (void)hipSetDevice(cur);
+  }
+  g_pool.clear();
 }
+}  // namespace
+
+void mem_trim() {
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  pool_trim_locked();
+}
+
+Arena::~Arena() {
+  if (ptrs_.empty()) return;
+  // queued work on these blocks ends before they can be handed out again (hipFree waited too)
+  (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  for (size_t i = 0; i < ptrs_.size(); ++i) g_pool.emplace(std::make_pair(dev_, sizes_[i]), ptrs_[i]);
+}
+
 void* Arena::raw(size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 8) + 255) & ~(size_t)255;
+  int dev = 0;
+  WB_HIP(hipGetDevice(&dev));
+  if (ptrs_.empty()) dev_ = dev;
+  WB_REQUIRE(dev == dev_, WB_EINVAL, "one arena serves one device");
   void* p = nullptr;
-  if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess)
-    throw Error{WB_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    auto it = g_pool.find(std::make_pair(dev, bytes));
+    if (it != g_pool.end()) {
+      p = it->second;
+      g_pool.erase(it);
+    }
+  }
+  if (!p) {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      mem_trim();
+      e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess)
+      throw Error{WB_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
   ptrs_.push_back(p);
+  sizes_.push_back(bytes);
   bytes_ += bytes;
   return p;
 }
@@ -241,29 +293,36 @@ void chebyshev(hipStream_t st, const Op& op, size_t len, const T* dinv, double l
   }
 }
 
+// Largest eigenvalue of D^-1 A from `steps` Jacobi-CG steps started from r (device, overwritten);
+// the CG scalars stay in device memory, one host read at the end.
 template <typename Op>
-double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, const std::vector<double>& b0,
-                   int steps, double* r, double* z, double* p, double* q) {
+double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, int steps, double* r,
+                   double* z, double* p, double* q) {
   hipStream_t st = s.st;
-  WB_HIP(hipMemcpyAsync(r, b0.data(), sizeof(double) * len, hipMemcpyHostToDevice, st));
+  WB_REQUIRE(steps >= 1 && 2 * steps + 1 <= LZ_SLOTS, WB_EINVAL, "lanczos_steps out of range");
+  // device scalars: rz[0..steps] then pq[0..steps-1]
+  double* rz = s.lz;
+  double* pq = s.lz + steps + 1;
   launch_mul<double>(st, len, dinv, r, z);
   WB_HIP(hipMemcpyAsync(p, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
-  double rz = dot_host(s, len, r, z);
-  std::vector<double> alphas, betas;
+  launch_dot<double>(st, len, r, z, s.red_partial, rz);
   for (int it = 0; it < steps; ++it) {
     op(p, q);
-    const double pq = dot_host(s, len, p, q);
-    if (!(rz > 0.0) || !(pq > 0.0)) break;
-    const double alpha = rz / pq;
-    launch_axpby<double>(st, len, -alpha, q, 1.0, r);
-    launch_mul<double>(st, len, dinv, r, z);
-    const double rz_new = dot_host(s, len, r, z);
-    const double beta = rz_new / rz;
-    alphas.push_back(alpha);
-    betas.push_back(beta);
-    rz = rz_new;
-    launch_axpby<double>(st, len, 1.0, z, beta, p);
-    if (!(rz > 0.0)) break;
+    launch_dot<double>(st, len, p, q, s.red_partial, pq + it);
+    launch_cg_r(st, len, q, dinv, r, z, rz + it, pq + it);
+    launch_dot<double>(st, len, r, z, s.red_partial, rz + it + 1);
+    launch_cg_p(st, len, z, p, rz + it + 1, rz + it);
+  }
+  std::vector<double> h(2 * steps + 1);
+  WB_HIP(hipMemcpyAsync(h.data(), s.lz, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  WB_HIP(hipStreamSynchronize(st));
+  std::vector<double> alphas, betas;
+  for (int it = 0; it < steps; ++it) {
+    const double rzj = h[it], pqj = h[steps + 1 + it], rzn = h[it + 1];
+    if (!(rzj > 0.0) || !(pqj > 0.0)) break;
+    alphas.push_back(rzj / pqj);
+    betas.push_back(rzn / rzj);
+    if (!(rzn > 0.0)) break;
   }
   const int m = (int)alphas.size();
   WB_REQUIRE(m > 0, WB_ENAN, "eigenvalue estimate failed (zero operator?)");
@@ -280,23 +339,11 @@ double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, cons
 // the mean removed for the Neumann Poisson levels).
 void set_cheb_bounds(Solver& s, Level<double>& L, unsigned long long seed) {
   hipStream_t st = s.st;
-  std::vector<double> b0;
-  splitmix_vector(seed, L.len, b0);
   const int M = L.k * L.N + 1;
-  if (L.dir) {
-    for (size_t i = 0; i < L.len; ++i) {
-      const size_t g = i % L.nn;
-      const int gi = (int)(g % M), gj = (int)((g / M) % M), gl = (int)(g / ((size_t)M * M));
-      if (gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1 || gl == 0 || gl == M - 1) b0[i] = 0.0;
-    }
-  } else {
-    double mean = 0.0;
-    for (double v : b0) mean += v;
-    mean /= (double)b0.size();
-    for (double& v : b0) v -= mean;
-  }
+  launch_splitmix_vec(st, L.len, seed, L.dir ? M : 0, L.x);
+  if (!L.dir) launch_remove_global_mean(st, L.len, L.x, s.red_partial, s.red_out + 12);
   auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out, s.opwork); };
-  const double lam = lanczos_max(s, op, L.len, L.dinv, b0, s.o.lanczos_steps, L.x, L.b, L.r, L.d);
+  const double lam = lanczos_max(s, op, L.len, L.dinv, s.o.lanczos_steps, L.x, L.b, L.r, L.d);
   L.lmin = 0.1 * lam;
   L.lmax = 1.1 * lam;
   for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
@@ -362,16 +409,17 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     if (!C.dir || !bnd) idx.push_back((int)i);
   }
   const int nd = (int)idx.size();
-  std::vector<double> Ad((size_t)nd * nd), col(C.len);
+  // all columns A e_j on the device, one copy to the host
+  std::vector<double> Ad((size_t)nd * nd), cols((size_t)nd * C.len);
+  double* dcols = ar.alloc<double>(cols.size());
   for (int j = 0; j < nd; ++j) {
-    launch_fill<double>(st, C.x, 0.0, C.len);
-    const double one = 1.0;
-    WB_HIP(hipMemcpyAsync(C.x + idx[j], &one, sizeof(double), hipMemcpyHostToDevice, st));
-    level_op<double>(st, C, C.x, C.t, s.opwork);
-    WB_HIP(hipMemcpyAsync(col.data(), C.t, sizeof(double) * C.len, hipMemcpyDeviceToHost, st));
-    WB_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < nd; ++i) Ad[(size_t)i * nd + j] = col[idx[i]];
+    launch_unit(st, C.len, (size_t)idx[j], C.x);
+    level_op<double>(st, C, C.x, dcols + (size_t)j * C.len, s.opwork);
   }
+  WB_HIP(hipMemcpyAsync(cols.data(), dcols, sizeof(double) * cols.size(), hipMemcpyDeviceToHost, st));
+  WB_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < nd; ++j)
+    for (int i = 0; i < nd; ++i) Ad[(size_t)i * nd + j] = cols[(size_t)j * C.len + idx[i]];
   for (int i = 0; i < nd; ++i)
     for (int j = i + 1; j < nd; ++j) {
       const double a = 0.5 * (Ad[(size_t)i * nd + j] + Ad[(size_t)j * nd + i]);
@@ -634,6 +682,23 @@ Solver::~Solver() {
   if (cap_st) (void)hipStreamDestroy(cap_st);
 }
 
+namespace {
+// Setup phase timing (stderr, with opts.verbose): waits for the stream at each mark.
+struct PhaseClock {
+  bool on;
+  hipStream_t st;
+  double t;
+  PhaseClock(bool v, hipStream_t s) : on(v), st(s), t(now_s()) {}
+  void mark(const char* what) {
+    if (!on) return;
+    (void)hipStreamSynchronize(st);
+    const double n = now_s();
+    fprintf(stderr, "setup %-28s %8.3f ms\n", what, 1e3 * (n - t));
+    t = n;
+  }
+};
+}  // namespace
+
 Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes, const wb_opts& o,
                       hipStream_t st) {
   WB_REQUIRE(m.k >= 2 && m.k <= 4, WB_EUNSUPPORTED, "Stokes solves need 2 <= k <= 4");
@@ -653,6 +718,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   Arena& ar = s.arena;
   s.red_partial = ar.alloc<double>(RED_BLOCKS * 128);
   s.red_out = ar.alloc<double>(16);
+  s.lz = ar.alloc<double>(LZ_SLOTS);
   const int n3 = (m.k + 1) * (m.k + 1) * (m.k + 1);
   {
     size_t wbytes = op_workspace_bytes(3, m.N, m.k, sizeof(double));
@@ -665,9 +731,12 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.mu_q = ar.alloc<double>((size_t)m.E * n3);
   WB_HIP(hipMemcpyAsync(s.mu_q, mu_q, sizeof(double) * m.E * n3, hipMemcpyDeviceToDevice, st));
 
+  PhaseClock clk(o.verbose != 0, st);
+  clk.mark("scratch + mu copy");
   s.pd.reset(new Precond<double>());
   Precond<double>& P = *s.pd;
   build_hierarchy(s, P.A, 3, s.mu_q, 1000);
+  clk.mark("velocity hierarchy");
   // learned coarse correction: velocity level Q1 on N/2 (if it is a smoothed level)
   for (int li = 0; li + 1 < (int)P.A.L.size(); ++li)
     if (P.A.L[li].k == 1 && 2 * P.A.L[li].N == m.N) {
@@ -706,21 +775,18 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     launch_poisson_coef(st, m.N, m.k, amps[side], s.mu_q, cq);
     build_hierarchy(s, P.Pois[side], 1, cq, side == 0 ? 2000 : 3000);
   }
+  clk.mark("weights + Poisson hierarchies");
   // Chebyshev bounds on the discontinuous K_w levels
   for (int side = 0; side < 2; ++side) {
-    std::vector<double> b0;
     const size_t pl = (size_t)m.E * m.np;
-    splitmix_vector(side == 0 ? 4000ULL : 5000ULL, pl, b0);
-    double mean = 0.0;
-    for (int e = 0; e < m.E; ++e) mean += b0[(size_t)e * m.np];
-    mean /= m.E;
-    for (int e = 0; e < m.E; ++e) b0[(size_t)e * m.np] -= mean;
+    launch_splitmix_vec(st, pl, side == 0 ? 4000ULL : 5000ULL, 0, P.pr);
+    launch_remove_mean<double>(st, m.E, m.np, P.pr, s.red_partial, s.red_out + 12);
     auto op = [&](const double* in, double* out) { apply_K<double>(s, P, side, in, out); };
-    const double lam =
-        lanczos_max(s, op, pl, P.dk[side], b0, o.lanczos_steps, P.pr, P.pd, P.pt, P.pm);
+    const double lam = lanczos_max(s, op, pl, P.dk[side], o.lanczos_steps, P.pr, P.pd, P.pt, P.pm);
     P.klmin[side] = 0.1 * lam;
     P.klmax[side] = 1.1 * lam;
   }
+  clk.mark("K_w bounds");
   if (o.precond_prec != WB_FP64) {
     s.pf.reset(new Precond<float>());
     Precond<float>& F = *s.pf;
@@ -736,6 +802,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     }
     alloc_work(s, F);
   }
+  clk.mark("FP32 copies");
   // Krylov space
   s.n_tot = (size_t)3 * m.nn + (size_t)m.E * m.np;
   const int R = o.restart;
@@ -746,6 +813,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.xvec = ar.alloc<double>(s.n_tot);
   s.hbuf = ar.alloc<double>((size_t)3 * (R + 2));
   s.mpartial = ar.alloc<double>((size_t)256 * (R + 2));
+  clk.mark("Krylov space");
   WB_HIP(hipStreamSynchronize(st));
   s.t_setup = now_s() - t0;
   return sp.release();

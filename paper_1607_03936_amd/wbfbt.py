@@ -101,6 +101,7 @@ SIGNATURES = {
     "wb_net_eval": (I, [I, I, VP, VP, VP, VP, VP, VP, ctypes.POINTER(D), VP]),
     "wb_net_adam": (I, [LL, VP, VP, VP, VP, I, D, VP]),
     "wb_net_feature": (I, [I, VP, VP, VP]),
+    "wb_mem_trim": (None, []),
     "wb_profile_enable": (None, [I]),
     "wb_profile_summary": (LL, [ctypes.c_char_p, LL, I]),
 }
