@@ -27,9 +27,36 @@ enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8, F_MF = 16, F_MF3 = 32 };
 // accumulate in LDS; values on internal brick faces pass through `work` (at least
 // op_workspace_bytes(NC, N, k, sizeof(T)) bytes) and are summed by a second kernel.
 size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size);
+
+// What an operator kernel does with each finished output value v at index j:
+//   EPI_STORE       y_j = v (or y_j += v when add)
+//   EPI_RESID       r_j = b_j - v
+//   EPI_CHEB_FIRST  r_j = b_j - v, dnew_j = alpha dinv_j r_j       (first Chebyshev step, x0 != 0;
+//                                                                 x += dnew is left to the next)
+//   EPI_CHEB_STEP   r_j -= v, dnew_j = alpha dold_j + beta dinv_j r_j, x_j += dnew_j
+//                   (+ dold_j when add_old: the deferred first correction)
+// Buffers written by an epilogue must not be read by the same operator (its input is dold or
+// x for EPI_CHEB_STEP / EPI_RESID, so dnew != dold).
+enum : int { EPI_STORE = 0, EPI_RESID = 1, EPI_CHEB_FIRST = 2, EPI_CHEB_STEP = 3 };
+template <typename T>
+struct Epi {
+  int mode = EPI_STORE;
+  int add_old = 0;
+  T alpha = T(0), beta = T(0);
+  T* r = nullptr;
+  const T* dold = nullptr;
+  T* dnew = nullptr;
+  T* x = nullptr;
+  const T* dinv = nullptr;
+  const T* b = nullptr;
+};
 template <typename T>
 void launch_op(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
                const T* pin, T* pout, const T* sin, bool add, void* work);
+// The same with an output epilogue (scatter operators, F_A / F_BT; not F_B alone).
+template <typename T>
+void launch_op_epi(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
+                   const T* pin, T* pout, const T* sin, bool add, void* work, const Epi<T>& ep);
 
 // Jacobi diagonal (not inverted) of the NC-component operator, accumulated into diag (zeroed).
 void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* coef, double* diag);

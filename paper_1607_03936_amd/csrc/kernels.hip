@@ -281,29 +281,26 @@ template <> struct Lds<5> { static constexpr int SY = 5, SZ = 25, SL = 125; };
 // element to its local node (x, y, z) of component c is handed to sink(c, x, y, z, value);
 // F_B writes the element's n_p pressure modes to pout.
 // Contains wavefront barriers: every lane of the wavefront must call it.
-template <int n, int NC, typename T, int F, int MF, typename Sink>
-__device__ inline void element_op(const bool valid, const int e, const int ex, const int ey,
-                                  const int ez, const int k, const int M, const int nn, const T hh,
-                                  const T* __restrict__ u, const T* __restrict__ coef,
-                                  const T* __restrict__ pin, T* __restrict__ pout,
-                                  const T* __restrict__ sin_, T* s, T* s2, const int r,
-                                  Sink&& sink) {
-  constexpr int NN = n * n, N3 = n * n * n;
-  constexpr int NP = (n - 1) * n * (n + 1) / 6;
-  constexpr int SY = Lds<n>::SY, SZ = Lds<n>::SZ;
-  const int a = r % n, b = r / n;
-  Frags fr;
-  if constexpr (MF) fr = make_frags<n>();
-  // z-line role (i, j) = (a, b)
-  const int gi = ex * k + a, gj = ey * k + b;
-  const bool bij = (gi == 0) || (gi == M - 1) || (gj == 0) || (gj == M - 1);
-  T S[NC][3][n];  // z-line role: gradients, then stresses, at (a, b, q)
-  T bq[n];
-  T cq[n];        // coefficient at (a, b, q)
+// Global inputs of one element in the z-line role (a, b): the node column of every component
+// (masked: 0 on Dirichlet nodes and for idle lanes) and the coefficient at the Gauss points.
+template <int n, int NC, typename T>
+struct ElemIn {
+  T uz[NC][n];
+  T cq[n];
+};
 
+// Loads of one element, issued up front from in-bounds addresses (index 0 for idle lanes);
+// masked values are selected away afterwards.
+template <int n, int NC, typename T, int F>
+__device__ inline void element_load(const bool valid, const int e, const int ex, const int ey,
+                                    const int ez, const int k, const int M, const int nn,
+                                    const T* __restrict__ u, const T* __restrict__ coef,
+                                    const T* __restrict__ sin_, const int r, ElemIn<n, NC, T>& in) {
+  constexpr int NN = n * n, N3 = n * n * n;
   if constexpr ((F & (F_A | F_B)) != 0) {
-    // All global loads of the element are issued up front from in-bounds addresses (index 0
-    // for idle lanes); masked values are selected away afterwards.
+    const int a = r % n, b = r / n;
+    const int gi = ex * k + a, gj = ey * k + b;
+    const bool bij = (gi == 0) || (gi == M - 1) || (gj == 0) || (gj == M - 1);
     int gidx[n];
     bool live[n];
 #pragma unroll
@@ -313,33 +310,49 @@ __device__ inline void element_op(const bool valid, const int e, const int ex, c
       live[l] = valid && !bnd;
       gidx[l] = valid ? gi + M * (gj + M * gl) : 0;
     }
-    T uz[NC][n];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int l = 0; l < n; ++l) uz[c][l] = u[(size_t)c * nn + gidx[l]];
+      for (int l = 0; l < n; ++l) in.uz[c][l] = u[(size_t)c * nn + gidx[l]];
     if constexpr ((F & F_A) != 0) {
       const size_t eb = (size_t)(valid ? e : 0) * N3 + b * n + a;
 #pragma unroll
-      for (int q = 0; q < n; ++q) cq[q] = coef[eb + q * NN];
+      for (int q = 0; q < n; ++q) in.cq[q] = coef[eb + q * NN];
     }
     if (sin_ != nullptr) {
 #pragma unroll
       for (int l = 0; l < n; ++l) {
         const T sl = sin_[gidx[l]];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) uz[c][l] *= sl;
+        for (int c = 0; c < NC; ++c) in.uz[c][l] *= sl;
       }
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int l = 0; l < n; ++l) uz[c][l] = live[l] ? uz[c][l] : T(0);
+      for (int l = 0; l < n; ++l) in.uz[c][l] = live[l] ? in.uz[c][l] : T(0);
+  }
+}
+
+template <int n, int NC, typename T, int F, int MF, typename Sink>
+__device__ inline void element_op(const bool valid, const int e, const int k, const T hh,
+                                  const ElemIn<n, NC, T>& in, const T* __restrict__ pin,
+                                  T* __restrict__ pout, T* s, T* s2, const int r, Sink&& sink) {
+  constexpr int NP = (n - 1) * n * (n + 1) / 6;
+  constexpr int SY = Lds<n>::SY, SZ = Lds<n>::SZ;
+  const int a = r % n, b = r / n;
+  Frags fr;
+  if constexpr (MF) fr = make_frags<n>();
+  T S[NC][3][n];  // z-line role: gradients, then stresses, at (a, b, q)
+  T bq[n];
+  const T* cq = in.cq;  // coefficient at (a, b, q)
+
+  if constexpr ((F & (F_A | F_B)) != 0) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T v[n], w[n];
       // z: interpolate the node column to the Gauss points
-      ctr<n, T, MF, C_B>(fr, uz[c], w);
+      ctr<n, T, MF, C_B>(fr, in.uz[c], w);
 #pragma unroll
       for (int q = 0; q < n; ++q) s[a + SY * b + SZ * q] = w[q];
       wave_sync();
@@ -533,8 +546,10 @@ k_op_gather(const int N, const int k, const int M, const int E, const int nn, co
     ez = q / N;
   }
   T* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
-  element_op<n, 3, T, F, MF>(valid, e, ex, ey, ez, k, M, nn, hh, u, nullptr, nullptr, pout, sin_, s0,
-                             s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
+  ElemIn<n, 3, T> in;
+  element_load<n, 3, T, F>(valid, e, ex, ey, ez, k, M, nn, u, nullptr, sin_, r, in);
+  element_op<n, 3, T, F, MF>(valid, e, k, hh, in, nullptr, pout, s0, s0 + (SLOTS + 1) * SL, r,
+                             [](int, int, int, int, T) {});
 }
 
 // Brick geometry of the scatter kernel: a block owns a BX x BY tile of elements and marches
@@ -576,20 +591,67 @@ inline BrickGeom brick_geom(int N, int k, int BX, int BY) {
   return g;
 }
 
+// Kernel-side copy of the brick geometry: the order and the tile shape are template constants,
+// the face array starts with the x planes; 32-bit fields (3 n_nodes < 2^31, face arrays smaller).
+struct BrickDev {
+  int N, M, nn, Bz, nbx, nby, nbz, fy, fz, per_comp;
+};
+inline BrickDev brick_dev(const BrickGeom& g) {
+  BrickDev d;
+  d.N = g.N;
+  d.M = g.M;
+  d.nn = g.nn;
+  d.Bz = g.Bz;
+  d.nbx = g.nbx;
+  d.nby = g.nby;
+  d.nbz = g.nbz;
+  d.fy = (int)g.fy;
+  d.fz = (int)g.fz;
+  d.per_comp = (int)g.per_comp;
+  return d;
+}
+
+// What happens to a finished node value v of output index j (see Epi in kernels.h); the mode is
+// a template constant, so a plain store carries none of the epilogue's arguments.
+template <int EP, typename T>
+__device__ __forceinline__ void emit(const Epi<T>& e, const size_t j, const T v, T* __restrict__ y,
+                                     const int add) {
+  if constexpr (EP == EPI_RESID) {
+    e.r[j] = e.b[j] - v;
+  } else if constexpr (EP == EPI_CHEB_FIRST) {
+    const T ri = e.b[j] - v;
+    e.r[j] = ri;
+    e.dnew[j] = e.alpha * e.dinv[j] * ri;
+  } else if constexpr (EP == EPI_CHEB_STEP) {
+    const T ri = e.r[j] - v;
+    e.r[j] = ri;
+    const T d0 = e.dold[j];
+    const T dn = e.alpha * d0 + e.beta * e.dinv[j] * ri;
+    e.dnew[j] = dn;
+    e.x[j] += e.add_old ? d0 + dn : dn;
+  } else {
+    y[j] = add ? y[j] + v : v;
+  }
+}
+
 // Store one finished node value: direct when the node is owned by this brick alone, else into
 // the face array of the first internal brick plane it lies on, slot s = sx + 2 sy + 4 sz
-// (s_d = 1 when this brick lies above that plane).
-template <int NC, typename T, bool DIR>
-__device__ inline void store_node(const BrickGeom& G, const int gx, const int gy, const int gz,
+// (s_d = 1 when this brick lies above that plane).  Dirichlet nodes emit 0.
+template <int n, int NC, typename T, bool DIR, int EP>
+__device__ inline void store_node(const BrickDev& G, const int gx, const int gy, const int gz,
                                   const int X0, const int Y0, const int Z0, const int X1,
                                   const int Y1, const int Z1, const T (&val)[NC],
-                                  T* __restrict__ y, T* __restrict__ face, const int add) {
+                                  T* __restrict__ y, T* __restrict__ face, const int add,
+                                  const Epi<T>& ep) {
+  constexpr int k = n - 1, KX = k * Tile<n>::BX, KY = k * Tile<n>::BY;
   const int M = G.M;
   const size_t g = (size_t)gx + (size_t)M * (gy + (size_t)M * gz);
   if (DIR && (gx == 0 || gx == M - 1 || gy == 0 || gy == M - 1 || gz == 0 || gz == M - 1)) {
-    if (!add)
+    // a Dirichlet node on an internal brick plane is visited by every adjacent brick: only the
+    // one for which it lies on no internal lower plane emits
+    if ((gx == X0 && X0 > 0) || (gy == Y0 && Y0 > 0) || (gz == Z0 && Z0 > 0)) return;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) y[(size_t)c * G.nn + g] = T(0);
+    for (int c = 0; c < NC; ++c) emit<EP>(ep, (size_t)c * G.nn + g, T(0), y, add);
     return;
   }
   const bool lx = gx == X0 && X0 > 0, ux = gx == X1 && X1 < M - 1;
@@ -597,23 +659,20 @@ __device__ inline void store_node(const BrickGeom& G, const int gx, const int gy
   const bool lz = gz == Z0 && Z0 > 0, uz = gz == Z1 && Z1 < M - 1;
   if (!(lx || ux || ly || uy || lz || uz)) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      T* p = &y[(size_t)c * G.nn + g];
-      *p = add ? *p + val[c] : val[c];
-    }
+    for (int c = 0; c < NC; ++c) emit<EP>(ep, (size_t)c * G.nn + g, val[c], y, add);
     return;
   }
   const int s = (lx ? 1 : 0) + 2 * (ly ? 1 : 0) + 4 * (lz ? 1 : 0);
-  size_t off;
+  int off;
   if (lx || ux) {
-    const int b = gx / (G.k * G.BX) - 1;
-    off = G.fx + ((size_t)(s * (G.nbx - 1) + b) * M + gz) * M + gy;
+    const int b = gx / KX - 1;
+    off = ((s * (G.nbx - 1) + b) * M + gz) * M + gy;
   } else if (ly || uy) {
-    const int b = gy / (G.k * G.BY) - 1;
-    off = G.fy + ((size_t)(s * (G.nby - 1) + b) * M + gz) * M + gx;
+    const int b = gy / KY - 1;
+    off = G.fy + ((s * (G.nby - 1) + b) * M + gz) * M + gx;
   } else {
-    const int b = gz / (G.k * G.Bz) - 1;
-    off = G.fz + ((size_t)(s * (G.nbz - 1) + b) * M + gy) * M + gx;
+    const int b = gz / (k * G.Bz) - 1;
+    off = G.fz + ((s * (G.nbz - 1) + b) * M + gy) * M + gx;
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) face[(size_t)c * G.per_comp + off] = val[c];
@@ -627,11 +686,12 @@ struct BrickThreads {
   static constexpr int NT = 64 * WAVES;
 };
 
-template <int n, int NC, typename T, int F, int MF>
+template <int n, int NC, typename T, int F, int MF, int EP>
 __global__ void __launch_bounds__(BrickThreads<n>::NT)
-k_op_brick(const BrickGeom G, const T hh, const T* __restrict__ u,
+k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
            T* __restrict__ y, const T* __restrict__ coef, const T* __restrict__ pin,
-           T* __restrict__ pout, const T* __restrict__ sin_, T* __restrict__ face, const int add) {
+           T* __restrict__ pout, const T* __restrict__ sin_, T* __restrict__ face, const int add,
+           const Epi<T> ep) {
   constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY, NE = BX * BY;
   constexpr int N3 = n * n * n, k = n - 1;
   constexpr int WX = k * BX + 1, WY = k * BY + 1, WP = WX * WY;   // window plane
@@ -653,16 +713,21 @@ k_op_brick(const BrickGeom G, const T hh, const T* __restrict__ u,
   const int ez0 = bz * G.Bz, ez1 = min(N, ez0 + G.Bz);
   const int Z0 = ez0 * k, Z1 = ez1 * k;
   for (int idx = t; idx < NC * (k + 1) * WP; idx += NT) win[idx] = T(0);
+  const bool valid = slot_ok && ex < N && ey < N;
   __syncthreads();
   for (int ez = ez0; ez < ez1; ++ez) {
-    const bool valid = slot_ok && ex < N && ey < N;
     const int e = ex + N * (ey + N * ez);
     T* wbase = win + (ly * k) * WX + lx * k;
     T* s0 = sm + (lane_ok ? le : SLOTS) * SL;
-    element_op<n, NC, T, F, MF>(valid, e, ex, ey, ez, k, M, G.nn, hh, u, coef, pin, pout, sin_, s0,
-                                s0 + (SLOTS + 1) * SL, r, [&](int c, int x, int yy, int z, T v) {
-                              if (valid) atomicAdd(wbase + (c * (k + 1) + z) * WP + yy * WX + x, v);
-                            });
+    // (loading the next layer before the plane flush raises the register peak of the Q3
+    // operator past 128 and costs a wave per SIMD: loads stay at the top of the layer)
+    ElemIn<n, NC, T> in;
+    element_load<n, NC, T, F>(valid, e, ex, ey, ez, k, M, G.nn, u, coef, sin_, r, in);
+    element_op<n, NC, T, F, MF>(valid, e, k, hh, in, pin, pout, s0, s0 + (SLOTS + 1) * SL, r,
+                                [&](int c, int x, int yy, int z, T v) {
+                                  if (valid)
+                                    atomicAdd(wbase + (c * (k + 1) + z) * WP + yy * WX + x, v);
+                                });
     __syncthreads();
     // planes z = ez k .. ez k + k - 1 are complete
     for (int idx = t; idx < k * WP; idx += NT) {
@@ -673,7 +738,7 @@ k_op_brick(const BrickGeom G, const T hh, const T* __restrict__ u,
       T val[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1) + l) * WP + w];
-      store_node<NC, T, (F & F_DIR) != 0>(G, gx, gy, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add);
+      store_node<n, NC, T, (F & F_DIR) != 0, EP>(G, gx, gy, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
     }
     __syncthreads();
     // shift the window: plane k becomes plane 0, the others restart at zero
@@ -693,21 +758,22 @@ k_op_brick(const BrickGeom G, const T hh, const T* __restrict__ u,
     T val[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1)) * WP + w];
-    store_node<NC, T, (F & F_DIR) != 0>(G, gx, gy, Z1, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add);
+    store_node<n, NC, T, (F & F_DIR) != 0, EP>(G, gx, gy, Z1, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
   }
 }
 
 // Sum the partial values on internal brick planes into y (x planes, then y planes not on an
 // x plane, then z planes on neither).
-template <int NC, typename T, bool DIR>
-__global__ void k_face_sum(const BrickGeom G, const T* __restrict__ face, T* __restrict__ y,
-                           const int add) {
+template <int n, int NC, typename T, bool DIR, int EP>
+__global__ void k_face_sum(const BrickDev G, const T* __restrict__ face, T* __restrict__ y,
+                           const int add, const Epi<T> ep) {
   const int M = G.M;
   const long long nx = (long long)(G.nbx - 1) * M * M, ny = (long long)(G.nby - 1) * M * M;
   const long long nz = (long long)(G.nbz - 1) * M * M;
   long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nx + ny + nz) return;
-  const int KX = G.k * G.BX, KY = G.k * G.BY, KZ = G.k * G.Bz;
+  constexpr int k = n - 1, KX = k * Tile<n>::BX, KY = k * Tile<n>::BY;
+  const int KZ = k * G.Bz;
   int gx, gy, gz, cat, b;
   if (idx < nx) {
     cat = 0;
@@ -747,7 +813,7 @@ __global__ void k_face_sum(const BrickGeom G, const T* __restrict__ face, T* __r
       for (int sx = 0; sx <= (on_x ? 1 : 0); ++sx) {
         const int s = sx + 2 * sy + 4 * sz;
         size_t off;
-        if (cat == 0) off = G.fx + ((size_t)(s * (G.nbx - 1) + b) * M + gz) * M + gy;
+        if (cat == 0) off = ((size_t)(s * (G.nbx - 1) + b) * M + gz) * M + gy;
         else if (cat == 1) off = G.fy + ((size_t)(s * (G.nby - 1) + b) * M + gz) * M + gx;
         else off = G.fz + ((size_t)(s * (G.nbz - 1) + b) * M + gy) * M + gx;
 #pragma unroll
@@ -755,10 +821,7 @@ __global__ void k_face_sum(const BrickGeom G, const T* __restrict__ face, T* __r
       }
   const size_t g = (size_t)gx + (size_t)M * (gy + (size_t)M * gz);
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    T* p = &y[(size_t)c * G.nn + g];
-    *p = add ? *p + val[c] : val[c];
-  }
+  for (int c = 0; c < NC; ++c) emit<EP>(ep, (size_t)c * G.nn + g, val[c], y, add);
 }
 
 struct ProfScope {
@@ -791,9 +854,9 @@ std::string op_key(int NC, int k, int N, int F, bool scale, size_t es, const cha
   return key;
 }
 
-template <int n, int NC, typename T, int F, int MF>
-void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, const T* pin, T* pout,
-               const T* sin, bool add, void* work) {
+template <int n, int NC, typename T, int F, int MF, int EP>
+void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, const T* pin,
+                  T* pout, const T* sin, bool add, void* work, const Epi<T>& ep) {
   const int M = k * N + 1, E = N * N * N, nn = M * M * M;
   const T hh = (T)(0.5 / N);
   const int Fk = F | (MF == 1 ? F_MF : 0) | (MF == 3 ? F_MF3 : 0);
@@ -805,41 +868,68 @@ void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, co
   } else {
     constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY;
     const BrickGeom G = brick_geom(N, k, BX, BY);
+    const BrickDev D = brick_dev(G);
     T* face = static_cast<T*>(work);
     {
       ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
-      hipLaunchKernelGGL((k_op_brick<n, NC, T, F, MF>), dim3(G.nbx * G.nby, G.nbz),
-                         dim3(BrickThreads<n>::NT), 0, st, G, hh, u, y, coef, pin, pout, sin, face,
-                         (int)add);
+      hipLaunchKernelGGL((k_op_brick<n, NC, T, F, MF, EP>), dim3(G.nbx * G.nby, G.nbz),
+                         dim3(BrickThreads<n>::NT), 0, st, D, hh, u, y, coef, pin, pout, sin, face,
+                         (int)add, ep);
     }
     const size_t tot = (size_t)(G.nbx + G.nby + G.nbz - 3) * G.plane;
     if (tot > 0) {
       ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), "-faces"));
-      hipLaunchKernelGGL((k_face_sum<NC, T, (F & F_DIR) != 0>), dim3(grid_for(tot, 256)), dim3(256),
-                         0, st, G, face, y, (int)add);
+      hipLaunchKernelGGL((k_face_sum<n, NC, T, (F & F_DIR) != 0, EP>), dim3(grid_for(tot, 256)),
+                         dim3(256), 0, st, D, face, y, (int)add, ep);
     }
   }
 }
 
+// Epilogues other than the plain store exist for the level operators (A with or without the
+// Dirichlet mask) only.
+template <int n, int NC, typename T, int F, int MF>
+void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, const T* pin, T* pout,
+               const T* sin, bool add, void* work, const Epi<T>& ep) {
+  if constexpr (F == F_A || F == (F_A | F_DIR)) {
+    switch (ep.mode) {
+      case EPI_RESID:
+        return op_launch_ep<n, NC, T, F, MF, EPI_RESID>(st, N, k, u, y, coef, pin, pout, sin, add,
+                                                        work, ep);
+      case EPI_CHEB_FIRST:
+        return op_launch_ep<n, NC, T, F, MF, EPI_CHEB_FIRST>(st, N, k, u, y, coef, pin, pout, sin,
+                                                             add, work, ep);
+      case EPI_CHEB_STEP:
+        return op_launch_ep<n, NC, T, F, MF, EPI_CHEB_STEP>(st, N, k, u, y, coef, pin, pout, sin,
+                                                            add, work, ep);
+      default:
+        break;
+    }
+  } else {
+    WB_REQUIRE(ep.mode == EPI_STORE, WB_EUNSUPPORTED, "epilogue not built for this operator");
+  }
+  op_launch_ep<n, NC, T, F, MF, EPI_STORE>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
+}
+
 template <int n, typename T, int MF>
 void op_dispatch_mf(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y,
-                    const T* coef, const T* pin, T* pout, const T* sin, bool add, void* work) {
+                    const T* coef, const T* pin, T* pout, const T* sin, bool add, void* work,
+                    const Epi<T>& ep) {
   if (NC == 1) {
     if (flags == F_A)
-      return op_launch<n, 1, T, F_A, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+      return op_launch<n, 1, T, F_A, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
   } else {
     switch (flags) {
       case F_A | F_DIR:
-        return op_launch<n, 3, T, F_A | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+        return op_launch<n, 3, T, F_A | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
       case F_A | F_BT | F_B | F_DIR:
         if constexpr (MF == 0)
           return op_launch<n, 3, T, F_A | F_BT | F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout,
-                                                                  sin, add, work);
+                                                                  sin, add, work, ep);
         break;
       case F_B | F_DIR:
-        return op_launch<n, 3, T, F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+        return op_launch<n, 3, T, F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
       case F_BT | F_DIR:
-        return op_launch<n, 3, T, F_BT | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work);
+        return op_launch<n, 3, T, F_BT | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
       default:
         break;
     }
@@ -849,18 +939,18 @@ void op_dispatch_mf(hipStream_t st, int flags, int NC, int N, int k, const T* u,
 
 template <int n, typename T>
 void op_dispatch_n(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
-                   const T* pin, T* pout, const T* sin, bool add, void* work) {
+                   const T* pin, T* pout, const T* sin, bool add, void* work, const Epi<T>& ep) {
   if ((flags & (F_MF | F_MF3)) != 0) {
     if constexpr (sizeof(T) == 4) {
       if ((flags & F_MF3) != 0)
         return op_dispatch_mf<n, T, 3>(st, flags & ~(F_MF | F_MF3), NC, N, k, u, y, coef, pin, pout,
-                                       sin, add, work);
+                                       sin, add, work, ep);
       return op_dispatch_mf<n, T, 1>(st, flags & ~F_MF, NC, N, k, u, y, coef, pin, pout, sin, add,
-                                     work);
+                                     work, ep);
     }
     throw Error{WB_EUNSUPPORTED, "BF16 contractions are built for FP32 data only"};
   }
-  return op_dispatch_mf<n, T, 0>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
+  return op_dispatch_mf<n, T, 0>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
 }
 
 // ------------------------------------------------------------------ diagonals
@@ -1130,13 +1220,17 @@ __global__ void k_coarsen_h(int Nf, int n, const double* __restrict__ Q, const d
 }
 
 template <typename T>
-__global__ void k_dense(int nd, const double* __restrict__ G, const int* __restrict__ idx,
-                        const T* __restrict__ x, T* __restrict__ y) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nd) return;
+__global__ void __launch_bounds__(256) k_dense(int nd, const double* __restrict__ G,
+                                               const int* __restrict__ idx,
+                                               const T* __restrict__ x, T* __restrict__ y) {
+  // one wavefront per row: coalesced reads of the row, wavefront sum
+  const int lane = threadIdx.x & 63, row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= nd) return;  // whole wavefronts leave together
   double s = 0.0;
-  for (int c = 0; c < nd; ++c) s += G[(size_t)r * nd + c] * (double)x[idx[c]];
-  y[idx[r]] = (T)s;
+  for (int c = lane; c < nd; c += 64) s += G[(size_t)row * nd + c] * (double)x[idx[c]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[idx[row]] = (T)s;
 }
 
 // ------------------------------------------------------------------ vectors
@@ -1382,15 +1476,27 @@ size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size) {
 }
 
 template <typename T>
-void launch_op(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
-               const T* pin, T* pout, const T* sin, bool add, void* work) {
+void launch_op_epi(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
+                   const T* pin, T* pout, const T* sin, bool add, void* work, const Epi<T>& ep) {
   switch (k + 1) {
-    case 2: return op_dispatch_n<2, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
-    case 3: return op_dispatch_n<3, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
-    case 4: return op_dispatch_n<4, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
-    case 5: return op_dispatch_n<5, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work);
+    case 2: return op_dispatch_n<2, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
+    case 3: return op_dispatch_n<3, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
+    case 4: return op_dispatch_n<4, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
+    case 5: return op_dispatch_n<5, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
     default: throw Error{WB_EUNSUPPORTED, "order not built"};
   }
+}
+template void launch_op_epi<double>(hipStream_t, int, int, int, int, const double*, double*,
+                                    const double*, const double*, double*, const double*, bool, void*,
+                                    const Epi<double>&);
+template void launch_op_epi<float>(hipStream_t, int, int, int, int, const float*, float*,
+                                   const float*, const float*, float*, const float*, bool, void*,
+                                   const Epi<float>&);
+
+template <typename T>
+void launch_op(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
+               const T* pin, T* pout, const T* sin, bool add, void* work) {
+  launch_op_epi<T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, Epi<T>{});
 }
 template void launch_op<double>(hipStream_t, int, int, int, int, const double*, double*,
                                 const double*, const double*, double*, const double*, bool, void*);
@@ -1527,7 +1633,7 @@ void launch_coarsen_h(hipStream_t st, int Nf, int n, const double* Q, const doub
 
 template <typename T>
 void launch_dense(hipStream_t st, int nd, const double* G, const int* idx, const T* x, T* y) {
-  hipLaunchKernelGGL((k_dense<T>), dim3(grid_for(nd, 64)), dim3(64), 0, st, nd, G, idx, x, y);
+  hipLaunchKernelGGL((k_dense<T>), dim3(grid_for(nd, 4)), dim3(256), 0, st, nd, G, idx, x, y);
 }
 template void launch_dense<double>(hipStream_t, int, const double*, const int*, const double*, double*);
 template void launch_dense<float>(hipStream_t, int, const double*, const int*, const float*, float*);

@@ -273,6 +273,59 @@ void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out, void* work
                nullptr, nullptr, false, work);
 }
 
+// Level operator with an output epilogue (see Epi): the Chebyshev updates and residuals of the
+// V-cycle are applied to each node value as the operator finishes it.
+template <typename T>
+void level_op_epi(Solver& s, const Level<T>& L, const T* in, const Epi<T>& e) {
+  launch_op_epi<T>(s.st, (L.dir ? (F_A | F_DIR) : F_A) | mf_flag<T>(s), L.NC, L.N, L.k, in, nullptr,
+                   L.coef, nullptr, nullptr, nullptr, false, s.opwork, e);
+}
+
+// Chebyshev-accelerated Jacobi (degree steps) on a level, operator and update fused: the
+// search directions alternate between L.d and L.t (the operator reads one while its epilogue
+// writes the other); with x0 != 0 the first correction is added to x by the next step.
+template <typename T>
+void cheb_level(Solver& s, Level<T>& L, const T* b, T* x, bool xzero) {
+  hipStream_t st = s.st;
+  const double theta = 0.5 * (L.lmax + L.lmin), delta = 0.5 * (L.lmax - L.lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  T* d0 = L.d;
+  T* d1 = L.t;
+  bool pending = false;
+  if (xzero) {
+    launch_cheb_first<T>(st, L.len, b, nullptr, L.dinv, (T)(1.0 / theta), d0, x, L.r, true);
+  } else {
+    Epi<T> e;
+    e.mode = EPI_CHEB_FIRST;
+    e.b = b;
+    e.r = L.r;
+    e.dnew = d0;
+    e.dinv = L.dinv;
+    e.alpha = (T)(1.0 / theta);
+    level_op_epi<T>(s, L, x, e);
+    pending = true;
+  }
+  for (int it = 1; it < s.o.cheb_degree; ++it) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    Epi<T> e;
+    e.mode = EPI_CHEB_STEP;
+    e.add_old = pending ? 1 : 0;
+    e.r = L.r;
+    e.dold = d0;
+    e.dnew = d1;
+    e.x = x;
+    e.dinv = L.dinv;
+    e.alpha = (T)(rho_new * rho);
+    e.beta = (T)(2.0 * rho_new / delta);
+    level_op_epi<T>(s, L, d0, e);
+    std::swap(d0, d1);
+    pending = false;
+    rho = rho_new;
+  }
+  if (pending) launch_axpby<T>(st, L.len, T(1), d0, T(1), x);
+}
+
 // Chebyshev-accelerated Jacobi (degree steps) for A x = b, A given as a callback.
 template <typename T, typename Op>
 void chebyshev(hipStream_t st, const Op& op, size_t len, const T* dinv, double lmin, double lmax,
@@ -559,16 +612,17 @@ void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
     launch_dense<T>(st, H.nd, H.G, H.gidx, b, x);
     return;
   }
-  auto op = [&](const T* in, T* out) { level_op<T>(st, L, in, out, s.opwork, mf_flag<T>(s)); };
-  const int deg = s.o.cheb_degree;
-  chebyshev<T>(st, op, L.len, L.dinv, L.lmin, L.lmax, deg, b, x, true, L.r, L.d, L.t);
-  op(x, L.t);
-  launch_sub<T>(st, L.len, b, L.t, L.r);
+  cheb_level<T>(s, L, b, x, true);
+  Epi<T> res;  // r = b - A x
+  res.mode = EPI_RESID;
+  res.b = b;
+  res.r = L.r;
+  level_op_epi<T>(s, L, x, res);
   Level<T>& C = H.L[li + 1];
   launch_kron<T>(st, L.R, L.NC, C.dir, false, L.r, C.b);
   vcycle<T>(s, H, li + 1, C.b, C.x);
   launch_kron<T>(st, L.P, L.NC, L.dir, true, C.x, x);
-  chebyshev<T>(st, op, L.len, L.dinv, L.lmin, L.lmax, deg, b, x, false, L.r, L.d, L.t);
+  cheb_level<T>(s, L, b, x, false);
   if (L.NC == 3 && s.learned && li == s.learned->lc && s.learned->trained && s.learned->active &&
       s.o.use_learned)
     learned_step<T>(s, L, b, x);
