@@ -581,7 +581,7 @@ inline BrickGeom brick_geom(int N, int k, int BX, int BY) {
   g.nbx = (N + BX - 1) / BX;
   g.nby = (N + BY - 1) / BY;
   const int tiles = g.nbx * g.nby;
-  g.Bz = std::max(2, std::min(N, (N * tiles) / 512));
+  g.Bz = std::max(1, std::min(N, (N * tiles) / 512));
   g.nbz = (N + g.Bz - 1) / g.Bz;
   g.plane = (size_t)g.M * g.M;
   g.fx = 0;
