@@ -264,14 +264,15 @@ __device__ __forceinline__ void ctr(const Frags& fr, const T (&v)[n], T (&out)[n
   }
 }
 
-// LDS layout of an element's scratch: value (x, y, z) at x + SY y + SZ z, slots SL apart.  The
-// strides keep the three line roles of a wavefront (z-, y- and x-lines) free of bank conflicts
-// beyond two-way (searched over padded strides for 64-lane ds_read_b64 access).
-template <int n> struct Lds;
-template <> struct Lds<2> { static constexpr int SY = 2, SZ = 4, SL = 8; };
-template <> struct Lds<3> { static constexpr int SY = 3, SZ = 9, SL = 27; };
-template <> struct Lds<4> { static constexpr int SY = 4, SZ = 18, SL = 71; };
-template <> struct Lds<5> { static constexpr int SY = 5, SZ = 25, SL = 125; };
+// LDS layout of an element's scratch for element size ES: value (x, y, z) at x + SY y + SZ z,
+// slots SL apart.  Padded strides spread the three line roles of a wavefront (z-, y- and
+// x-lines) over the banks; the Q3 FP64 strides were chosen by measured bank-conflict counts.
+template <int n, int ES> struct Lds;
+template <int ES> struct Lds<2, ES> { static constexpr int SY = 2, SZ = 4, SL = 8; };
+template <int ES> struct Lds<3, ES> { static constexpr int SY = 3, SZ = 9, SL = 27; };
+template <> struct Lds<4, 8> { static constexpr int SY = 4, SZ = 19, SL = 88; };
+template <> struct Lds<4, 4> { static constexpr int SY = 4, SZ = 18, SL = 71; };
+template <int ES> struct Lds<5, ES> { static constexpr int SY = 5, SZ = 25, SL = 125; };
 
 // Element computation shared by the operator kernels.  The n^2 lanes of an element take three
 // roles, always with a = r % n, b = r / n: the z-line (a, b, .), the y-line (a, ., b) or the
@@ -339,7 +340,7 @@ __device__ inline void element_op(const bool valid, const int e, const int k, co
                                   const ElemIn<n, NC, T>& in, const T* __restrict__ pin,
                                   T* __restrict__ pout, T* s, T* s2, const int r, Sink&& sink) {
   constexpr int NP = (n - 1) * n * (n + 1) / 6;
-  constexpr int SY = Lds<n>::SY, SZ = Lds<n>::SZ;
+  constexpr int SY = Lds<n, sizeof(T)>::SY, SZ = Lds<n, sizeof(T)>::SZ;
   const int a = r % n, b = r / n;
   Frags fr;
   if constexpr (MF) fr = make_frags<n>();
@@ -531,7 +532,7 @@ template <int n, typename T, int F, int MF>
 __global__ void __launch_bounds__(256)
 k_op_gather(const int N, const int k, const int M, const int E, const int nn, const T hh,
             const T* __restrict__ u, T* __restrict__ pout, const T* __restrict__ sin_) {
-  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n>::SL;
+  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n, sizeof(T)>::SL;
   __shared__ T sm[2 * (SLOTS + 1) * SL];
   int slot, r;
   bool lane_ok;
@@ -678,6 +679,14 @@ __device__ inline void store_node(const BrickDev& G, const int gx, const int gy,
   for (int c = 0; c < NC; ++c) face[(size_t)c * G.per_comp + off] = val[c];
 }
 
+// Strides of the LDS accumulation window (row, plane) for element size ES: padding spreads the
+// accumulations of neighbouring elements over the banks.
+template <int n, int ES>
+struct WinPad {
+  static constexpr int WX = (n - 1) * Tile<n>::BX + 1, WY = (n - 1) * Tile<n>::BY + 1;
+  static constexpr int WXS = WX, WPS = WX * WY;
+};
+
 // Scatter operator: y = op(u) (or y += op(u)), F_B output as well when requested.
 template <int n>
 struct BrickThreads {
@@ -694,11 +703,14 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
            const Epi<T> ep) {
   constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY, NE = BX * BY;
   constexpr int N3 = n * n * n, k = n - 1;
-  constexpr int WX = k * BX + 1, WY = k * BY + 1, WP = WX * WY;   // window plane
+  constexpr int WX = k * BX + 1, WY = k * BY + 1, WP = WX * WY;   // window plane (logical)
+  // padded strides of the window in LDS (row WXS, plane WPS)
+  constexpr int WXS = WinPad<n, sizeof(T)>::WXS, WPS = WinPad<n, sizeof(T)>::WPS;
+  static_assert(WXS >= WX && WPS >= WXS * WY, "window padding");
   constexpr int NT = BrickThreads<n>::NT, SLOTS = BrickThreads<n>::WAVES * WaveMap<n>::EPW;
-  constexpr int SL = Lds<n>::SL;
+  constexpr int SL = Lds<n, sizeof(T)>::SL;
   __shared__ T sm[2 * (SLOTS + 1) * SL];
-  __shared__ T win[NC * (k + 1) * WP];
+  __shared__ T win[NC * (k + 1) * WPS];
   const int N = G.N, M = G.M;
   const int t = threadIdx.x;
   int le, r;
@@ -712,12 +724,12 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
   const int X1 = X0 + k * BX, Y1 = Y0 + k * BY;
   const int ez0 = bz * G.Bz, ez1 = min(N, ez0 + G.Bz);
   const int Z0 = ez0 * k, Z1 = ez1 * k;
-  for (int idx = t; idx < NC * (k + 1) * WP; idx += NT) win[idx] = T(0);
+  for (int idx = t; idx < NC * (k + 1) * WPS; idx += NT) win[idx] = T(0);
   const bool valid = slot_ok && ex < N && ey < N;
   __syncthreads();
   for (int ez = ez0; ez < ez1; ++ez) {
     const int e = ex + N * (ey + N * ez);
-    T* wbase = win + (ly * k) * WX + lx * k;
+    T* wbase = win + (ly * k) * WXS + lx * k;
     T* s0 = sm + (lane_ok ? le : SLOTS) * SL;
     // (loading the next layer before the plane flush raises the register peak of the Q3
     // operator past 128 and costs a wave per SIMD: loads stay at the top of the layer)
@@ -726,7 +738,7 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
     element_op<n, NC, T, F, MF>(valid, e, k, hh, in, pin, pout, s0, s0 + (SLOTS + 1) * SL, r,
                                 [&](int c, int x, int yy, int z, T v) {
                                   if (valid)
-                                    atomicAdd(wbase + (c * (k + 1) + z) * WP + yy * WX + x, v);
+                                    atomicAdd(wbase + (c * (k + 1) + z) * WPS + yy * WXS + x, v);
                                 });
     __syncthreads();
     // planes z = ez k .. ez k + k - 1 are complete
@@ -737,16 +749,17 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
       if (gx >= M || gy >= M) continue;
       T val[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1) + l) * WP + w];
+      for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1) + l) * WPS + wy * WXS + wx];
       store_node<n, NC, T, (F & F_DIR) != 0, EP>(G, gx, gy, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
     }
     __syncthreads();
     // shift the window: plane k becomes plane 0, the others restart at zero
     for (int idx = t; idx < NC * WP; idx += NT) {
       const int c = idx / WP, w = idx - c * WP;
-      win[(c * (k + 1)) * WP + w] = win[(c * (k + 1) + k) * WP + w];
+      const int ws = (w / WX) * WXS + w % WX;
+      win[(c * (k + 1)) * WPS + ws] = win[(c * (k + 1) + k) * WPS + ws];
 #pragma unroll
-      for (int l = 1; l <= k; ++l) win[(c * (k + 1) + l) * WP + w] = T(0);
+      for (int l = 1; l <= k; ++l) win[(c * (k + 1) + l) * WPS + ws] = T(0);
     }
     __syncthreads();
   }
@@ -757,7 +770,7 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
     if (gx >= M || gy >= M) continue;
     T val[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1)) * WP + w];
+    for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1)) * WPS + wy * WXS + wx];
     store_node<n, NC, T, (F & F_DIR) != 0, EP>(G, gx, gy, Z1, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
   }
 }
