@@ -87,6 +87,10 @@ typedef struct {
                              -1 (default): -S~, the saddle matrix's own Schur
                              complement sign (the paper's S is its negation);
                              +1: eq. (3) as printed                              */
+  double assemble_mb;     /* Q1 multigrid levels whose assembled 27-point stencil
+                             takes at most this many MB (FP64) are applied as
+                             stencils instead of element kernels (32); the coarsest
+                             level is always assembled; 0: element kernels only   */
 } wb_opts;
 
 typedef struct {

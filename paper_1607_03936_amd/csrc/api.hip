@@ -96,6 +96,7 @@ void wb_opts_default(wb_opts* o) {
   o->verbose = 0;
   o->use_graph = 1;
   o->schur_sign = -1;
+  o->assemble_mb = 32.0;
 }
 
 const char* wb_last_error(void) { return g_err.c_str(); }

@@ -58,6 +58,20 @@ template <typename T>
 void launch_op_epi(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
                    const T* pin, T* pout, const T* sin, bool add, void* work, const Epi<T>& ep);
 
+// Assembled Q1 levels.  The level operator (A, with the Dirichlet mask when NC = 3; Neumann when
+// NC = 1) on N^3 Q1 elements is stored as a 27-point stencil per node:
+//   S[((o NC + c) NC + d) nn + i] = entry (node i, component c; node i + o, component d),
+//   o = (ox+1) + 3 (oy+1) + 9 (oz+1), ox, oy, oz in {-1, 0, 1}; nn = (N+1)^3.
+// assemble_q1 builds S (q1_stencil_len doubles) from the element kernel's own element matrices
+// in ae (q1_elem_matrix_len doubles, scratch).  launch_stencil_epi applies it with the epilogues
+// of launch_op_epi: the same operator up to rounding order.
+size_t q1_elem_matrix_len(int NC, int N);
+size_t q1_stencil_len(int NC, int N);
+void assemble_q1(hipStream_t st, int NC, int N, bool dir, const double* coef, double* ae, double* S);
+template <typename T>
+void launch_stencil_epi(hipStream_t st, int NC, int N, const T* S, const T* u, T* y, bool add,
+                        const Epi<T>& ep);
+
 // Jacobi diagonal (not inverted) of the NC-component operator, accumulated into diag (zeroed).
 void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* coef, double* diag);
 // dinv = 1/diag, 1 on Dirichlet nodes (if dir).
@@ -86,11 +100,15 @@ void launch_load(hipStream_t st, int N, int k, const double* f_q, double* F);
 void launch_poisson_coef(hipStream_t st, int N, int k, double amp, const double* mu_q, double* c_q);
 
 // Transfers: tensor product of a 1D sparse matrix (rows: cnt / col / val, width W).
+// lin21 marks the rows of linear interpolation between nested node lines with
+// M_fine = 2 M_coarse - 1 (weight 1 at shared nodes, 1/2 at midpoints: Q1 h-coarsening and the
+// Q2 -> Q1 p-step) or of its transpose; those transfers run in a kernel with the weights built in.
 struct Rows1D {
   int rows, cols, W;
   int* cnt;
   int* col;
   double* val;
+  int lin21;
 };
 template <typename T>
 void launch_kron(hipStream_t st, const Rows1D& R, int NC, bool dir, bool add, const T* in, T* out);
@@ -145,8 +163,6 @@ void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const dou
 void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int M, double* x);
 // x -= mean(x) (two-stage sum, deterministic)
 void launch_remove_global_mean(hipStream_t st, size_t n, double* x, double* partial, double* scratch);
-// x = e_j (unit vector of length n)
-void launch_unit(hipStream_t st, size_t n, size_t j, double* x);
 
 // Reductions into a device FP64 scalar (two stages, deterministic).
 template <typename T>

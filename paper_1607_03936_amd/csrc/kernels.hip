@@ -966,6 +966,172 @@ void op_dispatch_n(hipStream_t st, int flags, int NC, int N, int k, const T* u, 
   return op_dispatch_mf<n, T, 0>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
 }
 
+// ------------------------------------------------------------------ assembled Q1 levels
+// Element matrices of the Q1 level operator, taken from the element kernel itself: column
+// (j, d) is the element operator applied to the unit vector of local node j = jx + 2 jy + 4 jz,
+// component d (the zero vector when that node is a Dirichlet node of a masked operator).
+// ae[e][j NC + d][i NC + c]; rows of Dirichlet nodes are dropped by the gather.
+template <int NC, bool DIR>
+__global__ void __launch_bounds__(256)
+k_elem_matrix(const int N, const double hh, const double* __restrict__ coef, double* __restrict__ ae) {
+  constexpr int n = 2, EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n, 8>::SL, ND = 8 * NC;
+  __shared__ double sm[2 * (SLOTS + 1) * SL];
+  int slot, r;
+  bool lane_ok;
+  WaveMap<n>::map(threadIdx.x, slot, r, lane_ok);
+  const int E = N * N * N, M = N + 1;
+  const int e = blockIdx.x * SLOTS + slot;
+  const bool valid = lane_ok && e < E;
+  int ex = 0, ey = 0, ez = 0;
+  if (valid) {
+    ex = e % N;
+    ey = (e / N) % N;
+    ez = e / (N * N);
+  }
+  double* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
+  const int a = r % n, b = r / n;
+  ElemIn<n, NC, double> in;
+  const size_t eb = (size_t)(valid ? e : 0) * 8 + b * 2 + a;  // in bounds for idle lanes
+#pragma unroll
+  for (int q = 0; q < n; ++q) in.cq[q] = coef[eb + q * 4];
+  for (int col = 0; col < ND; ++col) {
+    const int j = col / NC, d = col % NC;
+    const int jx = j & 1, jy = (j >> 1) & 1, jz = j >> 2;
+    const int gx = ex + jx, gy = ey + jy, gz = ez + jz;
+    const bool dead = DIR && (gx == 0 || gx == M - 1 || gy == 0 || gy == M - 1 || gz == 0 || gz == M - 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+        in.uz[c][l] = (!dead && c == d && a == jx && b == jy && l == jz) ? 1.0 : 0.0;
+    double* out = ae + ((size_t)(valid ? e : 0) * ND + col) * ND;
+    element_op<n, NC, double, F_A, 0>(valid, e, 1, hh, in, nullptr, nullptr, s0,
+                                      s0 + (SLOTS + 1) * SL, r,
+                                      [&](int c, int x, int yy, int z, double v) {
+                                        if (valid) out[(x + 2 * yy + 4 * z) * NC + c] = v;
+                                      });
+  }
+}
+
+// 27-point stencil of an assembled Q1 level: S[((o NC + c) NC + d) nn + i] couples component c
+// of node i with component d of node i + offset o, o = (ox+1) + 3 (oy+1) + 9 (oz+1); it sums
+// the element-matrix entries of the elements holding both nodes.  Entries reaching outside the
+// mesh, rows of Dirichlet nodes (DIR) and columns of Dirichlet nodes are zero.
+template <int NC, bool DIR>
+__global__ void k_stencil_gather(const int N, const double* __restrict__ ae, double* __restrict__ S) {
+  constexpr int ND = 8 * NC;
+  const int M = N + 1, nn = M * M * M;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 27LL * nn) return;
+  const int o = (int)(idx / nn), i = (int)(idx % nn);
+  const int ix = i % M, iy = (i / M) % M, iz = i / (M * M);
+  const int jx = ix + o % 3 - 1, jy = iy + (o / 3) % 3 - 1, jz = iz + o / 9 - 1;
+  double acc[NC][NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int d = 0; d < NC; ++d) acc[c][d] = 0.0;
+  const bool row_dead = DIR && (ix == 0 || ix == M - 1 || iy == 0 || iy == M - 1 || iz == 0 || iz == M - 1);
+  const bool in_mesh = jx >= 0 && jx < M && jy >= 0 && jy < M && jz >= 0 && jz < M;
+  if (in_mesh && !row_dead) {
+    for (int ez = iz - 1; ez <= iz; ++ez) {
+      if (ez < 0 || ez >= N || jz < ez || jz > ez + 1) continue;
+      for (int ey = iy - 1; ey <= iy; ++ey) {
+        if (ey < 0 || ey >= N || jy < ey || jy > ey + 1) continue;
+        for (int ex = ix - 1; ex <= ix; ++ex) {
+          if (ex < 0 || ex >= N || jx < ex || jx > ex + 1) continue;
+          const size_t e = (size_t)ex + (size_t)N * (ey + (size_t)N * ez);
+          const int il = (ix - ex) + 2 * (iy - ey) + 4 * (iz - ez);
+          const int jl = (jx - ex) + 2 * (jy - ey) + 4 * (jz - ez);
+          const double* m = ae + e * ND * ND;
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int d = 0; d < NC; ++d) acc[c][d] += m[(jl * NC + d) * ND + il * NC + c];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int d = 0; d < NC; ++d) S[((size_t)(o * NC + c) * NC + d) * nn + i] = acc[c][d];
+}
+
+// y = S u for an assembled Q1 level (one thread per output component c and node i), with the
+// same epilogues as the element kernels.  One-wave blocks spread the small grids of the coarse
+// levels over more compute units.
+constexpr int STENCIL_BLOCK = 64;
+template <int NC, typename T, int EP>
+__global__ void __launch_bounds__(STENCIL_BLOCK)
+k_stencil(const int M, const T* __restrict__ S, const T* __restrict__ u, T* __restrict__ y,
+          const int add, const Epi<T> ep) {
+  const int nn = M * M * M;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)NC * nn) return;
+  const int c = (int)(idx / nn), i = (int)(idx % nn);
+  const int ix = i % M, iy = (i / M) % M, iz = i / (M * M);
+  // loads without branches (neighbours outside the mesh read node i and are selected away), so
+  // that a whole plane of offsets is in flight at once
+  bool inx[3], iny[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    inx[t] = ix + t - 1 >= 0 && ix + t - 1 < M;
+    iny[t] = iy + t - 1 >= 0 && iy + t - 1 < M;
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int oz = 0; oz < 3; ++oz) {
+    const bool inz = iz + oz - 1 >= 0 && iz + oz - 1 < M;
+    T sv[9][NC], uv[9][NC];
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 3; ++ox) {
+        const int p = ox + 3 * oy, o = p + 9 * oz;
+        const bool in = inz && iny[oy] && inx[ox];
+        const int j = in ? i + (ox - 1) + M * ((oy - 1) + M * (oz - 1)) : i;
+#pragma unroll
+        for (int d = 0; d < NC; ++d) {
+          sv[p][d] = S[((size_t)(o * NC + c) * NC + d) * nn + i];
+          uv[p][d] = u[(size_t)d * nn + j];
+        }
+      }
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 3; ++ox) {
+        const int p = ox + 3 * oy;
+        const bool in = inz && iny[oy] && inx[ox];
+#pragma unroll
+        for (int d = 0; d < NC; ++d) acc += in ? sv[p][d] * uv[p][d] : T(0);
+      }
+  }
+  emit<EP>(ep, (size_t)c * nn + i, acc, y, add);
+}
+
+template <int NC, typename T, int EP>
+void stencil_launch(hipStream_t st, int N, const T* S, const T* u, T* y, bool add, const Epi<T>& ep) {
+  const int M = N + 1;
+  const size_t tot = (size_t)NC * M * M * M;
+  char key[96];
+  snprintf(key, sizeof(key), "stencil nc=%d k=1 N=%d %s", NC, N, sizeof(T) == 8 ? "f64" : "f32");
+  ProfScope ps(st, key);
+  hipLaunchKernelGGL((k_stencil<NC, T, EP>), dim3(grid_for(tot, STENCIL_BLOCK)), dim3(STENCIL_BLOCK),
+                     0, st, M, S, u, y, (int)add, ep);
+}
+
+template <int NC, typename T>
+void stencil_dispatch(hipStream_t st, int N, const T* S, const T* u, T* y, bool add, const Epi<T>& ep) {
+  switch (ep.mode) {
+    case EPI_STORE: return stencil_launch<NC, T, EPI_STORE>(st, N, S, u, y, add, ep);
+    case EPI_RESID: return stencil_launch<NC, T, EPI_RESID>(st, N, S, u, y, add, ep);
+    case EPI_CHEB_FIRST: return stencil_launch<NC, T, EPI_CHEB_FIRST>(st, N, S, u, y, add, ep);
+    case EPI_CHEB_STEP: return stencil_launch<NC, T, EPI_CHEB_STEP>(st, N, S, u, y, add, ep);
+    default: throw Error{WB_EINVAL, "unknown epilogue"};
+  }
+}
+
 // ------------------------------------------------------------------ diagonals
 template <int n, int NC>
 __global__ void k_diag(const KT<n, double> tb, int N, int k, int M, int E, int nn, double hh, int dir,
@@ -1147,6 +1313,67 @@ __global__ void k_kron(int Mo, int Mi, int NC, int W, const int* __restrict__ cn
       const double vb = vc * val[oj * W + tb];
       const long long bb = bc + (long long)col[oj * W + tb] * Mi;
       for (int ta = 0; ta < cnt[oi]; ++ta) s += vb * val[oi * W + ta] * (double)inc[bb + col[oi * W + ta]];
+    }
+  }
+  out[idx] = add ? out[idx] + (T)s : (T)s;
+}
+
+// Linear interpolation between nested node grids, M_fine = 2 M_coarse - 1, and its transpose.
+// Prolongation: the fine node value is the mean of the coarse values at the 8 corners
+// (x0|x1) x (y0|y1) x (z0|z1), x0 = fx / 2, x1 = x0 + (fx odd): 1 at shared nodes, 1/2 along a
+// midpoint direction.  Restriction: weights (1/2, 1, 1/2) on the fine nodes 2c-1, 2c, 2c+1 of each
+// direction (inside the grid).  Dirichlet outputs (dir) are zeroed when !add, left alone when add.
+template <typename T, bool PROLONG>
+__global__ void __launch_bounds__(256)
+k_lin21(const int Mo, const int Mi, const int NC, const int dir, const int add,
+        const T* __restrict__ in, T* __restrict__ out) {
+  const long long no = (long long)Mo * Mo * Mo, ni = (long long)Mi * Mi * Mi;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= no * NC) return;
+  const int c = (int)(idx / no);
+  const long long o = idx % no;
+  const int ox = (int)(o % Mo), oy = (int)((o / Mo) % Mo), oz = (int)(o / ((long long)Mo * Mo));
+  if (dir && (ox == 0 || ox == Mo - 1 || oy == 0 || oy == Mo - 1 || oz == 0 || oz == Mo - 1)) {
+    if (!add) out[idx] = T(0);
+    return;
+  }
+  const T* inc = in + (size_t)c * ni;
+  double s = 0.0;
+  if constexpr (PROLONG) {
+    const int x0 = ox >> 1, y0 = oy >> 1, z0 = oz >> 1;
+    const int xs[2] = {x0, x0 + (ox & 1)}, ys[2] = {y0, y0 + (oy & 1)}, zs[2] = {z0, z0 + (oz & 1)};
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      v[t] = (double)inc[xs[t & 1] + (size_t)Mi * (ys[(t >> 1) & 1] + (size_t)Mi * zs[t >> 2])];
+    // pairwise means (exact where a pair is one node)
+    const double a0 = 0.5 * (v[0] + v[1]), a1 = 0.5 * (v[2] + v[3]);
+    const double a2 = 0.5 * (v[4] + v[5]), a3 = 0.5 * (v[6] + v[7]);
+    s = 0.5 * (0.5 * (a0 + a1) + 0.5 * (a2 + a3));
+  } else {
+    int xs[3], ys[3], zs[3];
+    double wx[3], wy[3], wz[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int fx = 2 * ox + t - 1, fy = 2 * oy + t - 1, fz = 2 * oz + t - 1;
+      const double w = t == 1 ? 1.0 : 0.5;
+      wx[t] = (fx >= 0 && fx < Mi) ? w : 0.0;
+      wy[t] = (fy >= 0 && fy < Mi) ? w : 0.0;
+      wz[t] = (fz >= 0 && fz < Mi) ? w : 0.0;
+      xs[t] = min(max(fx, 0), Mi - 1);
+      ys[t] = min(max(fy, 0), Mi - 1);
+      zs[t] = min(max(fz, 0), Mi - 1);
+    }
+#pragma unroll
+    for (int tz = 0; tz < 3; ++tz) {
+      double v[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        v[t] = (double)inc[xs[t % 3] + (size_t)Mi * (ys[t / 3] + (size_t)Mi * zs[tz])];
+      double sz = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) sz += wy[t / 3] * wx[t % 3] * v[t];
+      s += wz[tz] * sz;
     }
   }
   out[idx] = add ? out[idx] + (T)s : (T)s;
@@ -1467,11 +1694,6 @@ __global__ void k_sub_mean(size_t n, double* __restrict__ x, const double* __res
   if (i < n) x[i] -= *sum / (double)n;
 }
 
-__global__ void k_unit(size_t n, size_t j, double* __restrict__ x) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = i == j ? 1.0 : 0.0;
-}
-
 }  // namespace
 
 // ================================================================== launchers
@@ -1515,6 +1737,39 @@ template void launch_op<double>(hipStream_t, int, int, int, int, const double*, 
                                 const double*, const double*, double*, const double*, bool, void*);
 template void launch_op<float>(hipStream_t, int, int, int, int, const float*, float*, const float*,
                                const float*, float*, const float*, bool, void*);
+
+size_t q1_elem_matrix_len(int NC, int N) { return (size_t)N * N * N * 64 * NC * NC; }
+size_t q1_stencil_len(int NC, int N) { return (size_t)27 * NC * NC * (N + 1) * (N + 1) * (N + 1); }
+
+void assemble_q1(hipStream_t st, int NC, int N, bool dir, const double* coef, double* ae, double* S) {
+  WB_REQUIRE(NC == 1 || NC == 3, WB_EINVAL, "assemble_q1: NC must be 1 or 3");
+  const double hh = 0.5 / N;
+  const int E = N * N * N, M = N + 1;
+  const unsigned eg = grid_for(E, 4 * WaveMap<2>::EPW);
+  const unsigned sg = grid_for((size_t)27 * M * M * M, 256);
+  if (NC == 1) {
+    WB_REQUIRE(!dir, WB_EUNSUPPORTED, "assemble_q1: scalar levels are Neumann");
+    hipLaunchKernelGGL((k_elem_matrix<1, false>), dim3(eg), dim3(256), 0, st, N, hh, coef, ae);
+    hipLaunchKernelGGL((k_stencil_gather<1, false>), dim3(sg), dim3(256), 0, st, N, ae, S);
+  } else {
+    WB_REQUIRE(dir, WB_EUNSUPPORTED, "assemble_q1: vector levels are Dirichlet");
+    hipLaunchKernelGGL((k_elem_matrix<3, true>), dim3(eg), dim3(256), 0, st, N, hh, coef, ae);
+    hipLaunchKernelGGL((k_stencil_gather<3, true>), dim3(sg), dim3(256), 0, st, N, ae, S);
+  }
+  WB_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_stencil_epi(hipStream_t st, int NC, int N, const T* S, const T* u, T* y, bool add,
+                        const Epi<T>& ep) {
+  if (NC == 1) return stencil_dispatch<1, T>(st, N, S, u, y, add, ep);
+  if (NC == 3) return stencil_dispatch<3, T>(st, N, S, u, y, add, ep);
+  throw Error{WB_EINVAL, "launch_stencil_epi: NC must be 1 or 3"};
+}
+template void launch_stencil_epi<double>(hipStream_t, int, int, const double*, const double*,
+                                         double*, bool, const Epi<double>&);
+template void launch_stencil_epi<float>(hipStream_t, int, int, const float*, const float*, float*,
+                                        bool, const Epi<float>&);
 
 #define WB_BY_ORDER(k, ...)                                       \
   switch ((k) + 1) {                                              \
@@ -1604,6 +1859,15 @@ void launch_poisson_coef(hipStream_t st, int N, int k, double amp, const double*
 template <typename T>
 void launch_kron(hipStream_t st, const Rows1D& R, int NC, bool dir, bool add, const T* in, T* out) {
   const size_t tot = (size_t)R.rows * R.rows * R.rows * NC;
+  if (R.lin21) {
+    if (R.rows > R.cols)
+      hipLaunchKernelGGL((k_lin21<T, true>), dim3(grid_for(tot, 256)), dim3(256), 0, st, R.rows,
+                         R.cols, NC, (int)dir, (int)add, in, out);
+    else
+      hipLaunchKernelGGL((k_lin21<T, false>), dim3(grid_for(tot, 256)), dim3(256), 0, st, R.rows,
+                         R.cols, NC, (int)dir, (int)add, in, out);
+    return;
+  }
   hipLaunchKernelGGL((k_kron<T>), dim3(grid_for(tot, 256)), dim3(256), 0, st, R.rows, R.cols, NC,
                      R.W, R.cnt, R.col, R.val, (int)dir, (int)add, in, out);
 }
@@ -1756,9 +2020,6 @@ void launch_cg_r(hipStream_t st, size_t n, const double* q, const double* dinv, 
 void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const double* rz_new,
                  const double* rz_old) {
   hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n, 256)), dim3(256), 0, st, n, z, p, rz_new, rz_old);
-}
-void launch_unit(hipStream_t st, size_t n, size_t j, double* x) {
-  hipLaunchKernelGGL(k_unit, dim3(grid_for(n, 256)), dim3(256), 0, st, n, j, x);
 }
 
 void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int M, double* x) {

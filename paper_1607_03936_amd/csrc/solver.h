@@ -47,6 +47,7 @@ struct Level {
   T *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
   Rows1D P{}, R{};         // prolongation from / restriction to the next coarser level
   double* Q = nullptr;     // coefficient coarsening matrix from the next finer level
+  T* S = nullptr;          // assembled 27-point stencil (Q1 levels within the size limit), else null
 };
 
 template <typename T>
@@ -105,6 +106,8 @@ struct Solver {
   double* red_partial = nullptr;  // reduction scratch
   double* red_out = nullptr;      // [16] device scalars
   double* lz = nullptr;           // [LZ_SLOTS] Lanczos scalars
+  double* ae = nullptr;           // element-matrix scratch of the Q1 assembly
+  size_t ae_len = 0;
   // Krylov space
   size_t n_tot = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hbuf = nullptr, *mpartial = nullptr;

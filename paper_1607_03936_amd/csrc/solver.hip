@@ -196,6 +196,7 @@ Rows1D upload_rows(Arena& ar, const std::vector<std::vector<std::pair<int, doubl
   o.rows = R;
   o.cols = ncols;
   o.W = W;
+  o.lin21 = 0;
   o.cnt = ar.alloc<int>(R);
   o.col = ar.alloc<int>((size_t)R * W);
   o.val = ar.alloc<double>((size_t)R * W);
@@ -225,6 +226,16 @@ void make_transfer(Arena& ar, int Nc, int kc, int Nf, int kf, Rows1D& P, Rows1D&
     for (auto& cv : prow[i]) rrow[cv.first].push_back({i, cv.second});
   P = upload_rows(ar, prow, Mc);
   R = upload_rows(ar, rrow, Mf);
+  bool lin = Mf == 2 * Mc - 1;
+  for (int i = 0; lin && i < Mf; ++i) {
+    const auto& r = prow[i];
+    if (i % 2 == 0)
+      lin = r.size() == 1 && r[0].first == i / 2 && std::fabs(r[0].second - 1.0) < 1e-13;
+    else
+      lin = r.size() == 2 && r[0].first == i / 2 && r[1].first == i / 2 + 1 &&
+            std::fabs(r[0].second - 0.5) < 1e-13 && std::fabs(r[1].second - 0.5) < 1e-13;
+  }
+  P.lin21 = R.lin21 = lin ? 1 : 0;
 }
 
 // Coarsening matrix Q[qc][(s, qf)] of the L2 adjoint of element-wise interpolation.
@@ -267,8 +278,11 @@ std::vector<double> make_bhat(int k) {
   return bh;
 }
 
+// Level operator: the assembled stencil where the level has one, else the element kernels
+// (`extra` selects their BF16 contractions).
 template <typename T>
 void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out, void* work, int extra = 0) {
+  if (L.S) return launch_stencil_epi<T>(st, L.NC, L.N, L.S, in, out, false, Epi<T>{});
   launch_op<T>(st, (L.dir ? (F_A | F_DIR) : F_A) | extra, L.NC, L.N, L.k, in, out, L.coef, nullptr,
                nullptr, nullptr, false, work);
 }
@@ -277,8 +291,26 @@ void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out, void* work
 // V-cycle are applied to each node value as the operator finishes it.
 template <typename T>
 void level_op_epi(Solver& s, const Level<T>& L, const T* in, const Epi<T>& e) {
+  if (L.S) return launch_stencil_epi<T>(s.st, L.NC, L.N, L.S, in, nullptr, false, e);
   launch_op_epi<T>(s.st, (L.dir ? (F_A | F_DIR) : F_A) | mf_flag<T>(s), L.NC, L.N, L.k, in, nullptr,
                    L.coef, nullptr, nullptr, nullptr, false, s.opwork, e);
+}
+
+// Q1 levels are assembled into 27-point stencils when the stencil fits the size limit
+// (assemble_mb); the coarsest level always is (its dense inverse is built from the stencil).
+bool assembles(const Solver& s, int NC, int N, int k, bool coarsest) {
+  if (k != 1) return false;
+  return coarsest || 8.0 * (double)q1_stencil_len(NC, N) <= s.o.assemble_mb * 1e6;
+}
+
+// (Re)build the stencil of an assembled level from its current coefficient.
+void assemble_level(Solver& s, Level<double>& L) {
+  const size_t need = q1_elem_matrix_len(L.NC, L.N);
+  if (s.ae_len < need) {
+    s.ae = s.arena.alloc<double>(need);
+    s.ae_len = need;
+  }
+  assemble_q1(s.st, L.NC, L.N, L.dir, L.coef, s.ae, L.S);
 }
 
 // Chebyshev-accelerated Jacobi (degree steps) on a level, operator and update fused: the
@@ -441,6 +473,10 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     launch_fill<double>(st, L.dinv, 0.0, L.len);
     launch_diag(st, NC, L.N, L.k, L.dir, L.coef, L.dinv);
     launch_invert_diag(st, NC, L.N, L.k, L.dir, L.dinv);
+    if (assembles(s, NC, L.N, L.k, li + 1 == nl)) {
+      L.S = ar.alloc<double>(q1_stencil_len(NC, L.N));
+      assemble_level(s, L);
+    }
     L.x = ar.alloc<double>(L.len);
     L.b = ar.alloc<double>(L.len);
     L.r = ar.alloc<double>(L.len);
@@ -462,17 +498,26 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     if (!C.dir || !bnd) idx.push_back((int)i);
   }
   const int nd = (int)idx.size();
-  // all columns A e_j on the device, one copy to the host
-  std::vector<double> Ad((size_t)nd * nd), cols((size_t)nd * C.len);
-  double* dcols = ar.alloc<double>(cols.size());
-  for (int j = 0; j < nd; ++j) {
-    launch_unit(st, C.len, (size_t)idx[j], C.x);
-    level_op<double>(st, C, C.x, dcols + (size_t)j * C.len, s.opwork);
-  }
-  WB_HIP(hipMemcpyAsync(cols.data(), dcols, sizeof(double) * cols.size(), hipMemcpyDeviceToHost, st));
+  // the dense matrix from the coarsest level's stencil (one copy to the host)
+  WB_REQUIRE(C.S != nullptr, WB_EUNSUPPORTED, "coarsest level is not Q1");
+  std::vector<double> Sh(q1_stencil_len(NC, C.N)), Ad((size_t)nd * nd, 0.0);
+  WB_HIP(hipMemcpyAsync(Sh.data(), C.S, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost, st));
   WB_HIP(hipStreamSynchronize(st));
-  for (int j = 0; j < nd; ++j)
-    for (int i = 0; i < nd; ++i) Ad[(size_t)i * nd + j] = cols[(size_t)j * C.len + idx[i]];
+  std::vector<int> pos(C.len, -1);
+  for (int i = 0; i < nd; ++i) pos[idx[i]] = i;
+  for (int i = 0; i < nd; ++i) {
+    const int c = (int)(idx[i] / C.nn), g = (int)(idx[i] % C.nn);
+    const int gx = g % M, gy = (g / M) % M, gz = g / (M * M);
+    for (int o = 0; o < 27; ++o) {
+      const int jx = gx + o % 3 - 1, jy = gy + (o / 3) % 3 - 1, jz = gz + o / 9 - 1;
+      if (jx < 0 || jx >= M || jy < 0 || jy >= M || jz < 0 || jz >= M) continue;
+      const int j = jx + M * (jy + M * jz);
+      for (int d = 0; d < NC; ++d) {
+        const int pj = pos[(size_t)d * C.nn + j];
+        if (pj >= 0) Ad[(size_t)i * nd + pj] += Sh[((size_t)(o * NC + c) * NC + d) * C.nn + g];
+      }
+    }
+  }
   for (int i = 0; i < nd; ++i)
     for (int j = i + 1; j < nd; ++j) {
       const double a = 0.5 * (Ad[(size_t)i * nd + j] + Ad[(size_t)j * nd + i]);
@@ -532,6 +577,11 @@ void cast_hierarchy(Solver& s, const Hierarchy<double>& Hd, Hierarchy<float>& Hf
     launch_cast<double, float>(st, ncoef, D.coef, L.coef);
     L.dinv = ar.alloc<float>(L.len);
     launch_cast<double, float>(st, L.len, D.dinv, L.dinv);
+    if (D.S) {
+      const size_t ns = q1_stencil_len(D.NC, D.N);
+      L.S = ar.alloc<float>(ns);
+      launch_cast<double, float>(st, ns, D.S, L.S);
+    }
     L.x = ar.alloc<float>(L.len);
     L.b = ar.alloc<float>(L.len);
     L.r = ar.alloc<float>(L.len);
@@ -761,6 +811,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   WB_REQUIRE(o.a_l >= 1.0 && o.a_r >= 1.0, WB_EINVAL, "boundary amplification must be >= 1");
   WB_REQUIRE(o.p_schedule == 0 || o.p_schedule == 1, WB_EINVAL, "p_schedule must be 0 or 1");
   WB_REQUIRE(o.schur_sign == 1 || o.schur_sign == -1, WB_EINVAL, "schur_sign must be 1 or -1");
+  WB_REQUIRE(o.assemble_mb >= 0.0, WB_EINVAL, "assemble_mb must be >= 0");
   WB_REQUIRE(o.precond_prec >= WB_FP64 && o.precond_prec <= WB_BF16X1, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
@@ -1199,6 +1250,8 @@ void learned_train(Solver& s, int n_fields, const int* n_sinkers, const double* 
     const int n = L.k + 1;
     L.coef = ar.alloc<double>((size_t)L.E * n * n * n);
     L.dinv = ar.alloc<double>(L.len);
+    // each field's own stencil on the smoothed assembled levels (the coarsest solve is shared)
+    L.S = (A.L[lc + j].S && j + 1 < T.L.size()) ? ar.alloc<double>(q1_stencil_len(3, L.N)) : nullptr;
     for (double** v : {&L.x, &L.b, &L.r, &L.d, &L.t}) *v = ar.alloc<double>(L.len);
   }
   T.nd = A.nd;
@@ -1239,6 +1292,7 @@ void learned_train(Solver& s, int n_fields, const int* n_sinkers, const double* 
       launch_fill<double>(st, L.dinv, 0.0, L.len);
       launch_diag(st, 3, L.N, L.k, true, L.coef, L.dinv);
       launch_invert_diag(st, 3, L.N, L.k, true, L.dinv);
+      if (L.S) assemble_level(s, L);
       for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
     }
     for (size_t j = 0; j + 1 < T.L.size(); ++j)

@@ -31,7 +31,8 @@ class wb_opts(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("precond_prec", ctypes.c_int),
                 ("use_learned", ctypes.c_int), ("p_schedule", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("schur_sign", ctypes.c_int)]
+                ("schur_sign", ctypes.c_int),
+                ("assemble_mb", ctypes.c_double)]
 
 
 class wb_report(ctypes.Structure):
@@ -153,7 +154,10 @@ def _ptr(t, dtype=None, numel=None):
 def opts(**kw) -> wb_opts:
     o = wb_opts()
     lib().wb_opts_default(ctypes.byref(o))
+    names = {f[0] for f in wb_opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solver option {k!r}")
         setattr(o, k, v)
     return o
 
