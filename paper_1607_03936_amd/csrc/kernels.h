@@ -53,7 +53,8 @@ struct Epi {
 template <typename T>
 void launch_op(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
                const T* pin, T* pout, const T* sin, bool add, void* work);
-// The same with an output epilogue (scatter operators, F_A / F_BT; not F_B alone).
+// The same with an output epilogue: built for the level operators (F_A, F_A | F_DIR; node
+// outputs) and for the divergence F_B | F_DIR (pressure outputs pout, indexed e n_p + m).
 template <typename T>
 void launch_op_epi(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
                    const T* pin, T* pout, const T* sin, bool add, void* work, const Epi<T>& ep);
@@ -71,6 +72,26 @@ void assemble_q1(hipStream_t st, int NC, int N, bool dir, const double* coef, do
 template <typename T>
 void launch_stencil_epi(hipStream_t st, int NC, int N, const T* S, const T* u, T* y, bool add,
                         const Epi<T>& ep);
+
+// Coarse tail of a scalar (Neumann) V-cycle in one workgroup: on an assembled Q1 level with
+// M^3 <= TAIL_MAX nodes (stencil S, inverse diagonal dinv), Chebyshev-Jacobi pre-smoothing from
+// x = 0 (deg steps; inv_theta and the step coefficients alpha[it], beta[it], it = 1..deg-1, of
+// the level's interval), residual, restriction to the next level (Mc = (M+1)/2 nodes per
+// direction, linear 2:1 weights), the dense coarsest solve xc[gidx[r]] = sum_c G[r,c] bc[gidx[c]]
+// (nd = Mc^3 rows), prolongation and post-smoothing.  x = V-cycle(b), b and x of length M^3.
+constexpr int TAIL_THREADS = 1024, TAIL_MAX = 1024, TAIL_MAXDEG = 8;
+template <typename T>
+struct TailArgs {
+  int M = 0, Mc = 0, nd = 0, deg = 0;
+  const T* S = nullptr;
+  const T* dinv = nullptr;
+  const double* G = nullptr;
+  const int* gidx = nullptr;
+  T inv_theta = T(0);
+  T alpha[TAIL_MAXDEG] = {}, beta[TAIL_MAXDEG] = {};
+};
+template <typename T>
+void launch_vcycle_tail(hipStream_t st, const TailArgs<T>& a, const T* b, T* x);
 
 // Jacobi diagonal (not inverted) of the NC-component operator, accumulated into diag (zeroed).
 void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* coef, double* diag);
@@ -139,10 +160,6 @@ void launch_scale_nodes(hipStream_t st, int nn, int NC, const T* s, const T* x, 
 template <typename T>
 void launch_cheb_first(hipStream_t st, size_t n, const T* b, const T* t, const T* dinv, T inv_theta,
                        T* d, T* x, T* r, bool xzero);
-// Chebyshev: r -= t, d = alpha d + beta dinv r, x += d
-template <typename T>
-void launch_cheb_step(hipStream_t st, size_t n, const T* t, const T* dinv, T alpha, T beta, T* d,
-                      T* x, T* r);
 // y = a x
 template <typename T> void launch_scal(hipStream_t st, size_t n, T a, const T* x, T* y);
 // zero the boundary nodes of an NC-component nodal vector with M nodes per direction

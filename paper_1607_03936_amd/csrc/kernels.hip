@@ -280,7 +280,7 @@ template <int ES> struct Lds<5, ES> { static constexpr int SY = 5, SZ = 25, SL =
 // between roles through the element's LDS scratch s, s2 (layout of Lds<n>).
 // Components are processed one after the other.  For F_A / F_BT the contribution of the
 // element to its local node (x, y, z) of component c is handed to sink(c, x, y, z, value);
-// F_B writes the element's n_p pressure modes to pout.
+// F_B hands each of the element's n_p pressure modes to psink(e n_p + m, value).
 // Contains wavefront barriers: every lane of the wavefront must call it.
 // Global inputs of one element in the z-line role (a, b): the node column of every component
 // (masked: 0 on Dirichlet nodes and for idle lanes) and the coefficient at the Gauss points.
@@ -335,15 +335,163 @@ __device__ inline void element_load(const bool valid, const int e, const int ex,
   }
 }
 
-template <int n, int NC, typename T, int F, int MF, typename Sink>
+template <int n, int NC, typename T, int F, int MF, typename PSink, typename Sink>
 __device__ inline void element_op(const bool valid, const int e, const int k, const T hh,
                                   const ElemIn<n, NC, T>& in, const T* __restrict__ pin,
-                                  T* __restrict__ pout, T* s, T* s2, const int r, Sink&& sink) {
+                                  PSink&& psink, T* s, T* s2, const int r, Sink&& sink) {
   constexpr int NP = (n - 1) * n * (n + 1) / 6;
   constexpr int SY = Lds<n, sizeof(T)>::SY, SZ = Lds<n, sizeof(T)>::SZ;
   const int a = r % n, b = r / n;
   Frags fr;
   if constexpr (MF) fr = make_frags<n>();
+  constexpr int FC = F & (F_A | F_B | F_BT);
+
+  if constexpr (NC == 3 && FC == F_B) {
+    // Divergence alone: component c needs only its derivative in direction c, taken right after
+    // the interpolation in that direction; the sum is formed in the x-line role (x Gauss point
+    // q, y Gauss point a, z Gauss point b), then projected onto the Legendre modes.
+    T dv[n];
+#pragma unroll
+    for (int q = 0; q < n; ++q) dv[q] = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T v[n], w[n];
+      ctr<n, T, MF, C_B>(fr, in.uz[c], w);
+      if (c == 2) {
+        ctr<n, T, MF, C_D>(fr, w, v);
+#pragma unroll
+        for (int q = 0; q < n; ++q) w[q] = v[q];
+      }
+#pragma unroll
+      for (int q = 0; q < n; ++q) s[a + SY * b + SZ * q] = w[q];
+      wave_sync();
+      // y-line (a, ., b), in place
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
+      ctr<n, T, MF, C_B>(fr, v, w);
+      if (c == 1) {
+        ctr<n, T, MF, C_D>(fr, w, v);
+#pragma unroll
+        for (int q = 0; q < n; ++q) w[q] = v[q];
+      }
+#pragma unroll
+      for (int q = 0; q < n; ++q) s[a + SY * q + SZ * b] = w[q];
+      wave_sync();
+      // x-line (., a, b)
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
+      ctr<n, T, MF, C_B>(fr, v, w);
+      if (c == 0) {
+        ctr<n, T, MF, C_D>(fr, w, v);
+#pragma unroll
+        for (int q = 0; q < n; ++q) w[q] = v[q];
+      }
+#pragma unroll
+      for (int q = 0; q < n; ++q) dv[q] += w[q];
+      wave_sync();
+    }
+    // project -(h/2)^2 w3 div u onto the Legendre modes: x first (mode ma), then y and z
+    const T wab = Wg<n, T>(a) * Wg<n, T>(b);
+#pragma unroll
+    for (int q = 0; q < n; ++q) dv[q] = -hh * hh * wab * Wg<n, T>(q) * dv[q];
+#pragma unroll
+    for (int c = 0; c < n - 1; ++c) {
+      T acc = T(0);
+#pragma unroll
+      for (int q = 0; q < n; ++q) acc += Lg<n, T>(c, q) * dv[q];
+      s[c + SY * a + SZ * b] = acc;
+    }
+    wave_sync();
+    if (valid && r < NP) {
+      const int ma = CT<n>::t.ma[r], mb = CT<n>::t.mb[r], mc = CT<n>::t.mc[r];
+      T acc = T(0);
+#pragma unroll
+      for (int kk = 0; kk < n; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < n; ++jj)
+          acc += Lg<n, T>(mb, jj) * Lg<n, T>(mc, kk) * s[ma + SY * jj + SZ * kk];
+      psink((size_t)e * NP + r, acc);
+    }
+    wave_sync();
+    return;
+  }
+
+  if constexpr (NC == 3 && FC == F_BT) {
+    // Gradient alone: the weighted pressure vv at the Gauss points is shared by the three
+    // components, u_c = (B^T Dh^T)_c (B^T)_others vv, so the transposed contractions are
+    // factored: z: A = B^T vv, Z = B^T Dh^T vv; y: from A both B^T and B^T Dh^T, from Z B^T;
+    // x: the last factor of each component.
+    T La[n - 1], Lb[n - 1];
+#pragma unroll
+    for (int m = 0; m < n - 1; ++m) {
+      La[m] = Lg<n, T>(m, a);
+      Lb[m] = Lg<n, T>(m, b);
+    }
+    const T wab = Wg<n, T>(a) * Wg<n, T>(b);
+    T vv[n];
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      T pq = T(0);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T pmv = valid ? pin[(size_t)e * NP + m] : T(0);
+        pq += pmv * La[CT<n>::t.ma[m]] * Lb[CT<n>::t.mb[m]] * Lg<n, T>(CT<n>::t.mc[m], q);
+      }
+      vv[q] = -hh * hh * wab * Wg<n, T>(q) * pq;
+    }
+    T v[n], w[n], A[n];
+    // z-line (a, b, .): Gauss points -> z nodes
+    ctr<n, T, MF, C_BT>(fr, vv, A);
+    ctr<n, T, MF, C_DT>(fr, vv, w);
+    ctr<n, T, MF, C_BT>(fr, w, v);
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      s[a + SY * b + SZ * l] = A[l];
+      s2[a + SY * b + SZ * l] = v[l];
+    }
+    wave_sync();
+    // y-line (a, ., b) with a the x Gauss point and b the z node, in place
+    T by[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = s[a + SY * m + SZ * b];
+    ctr<n, T, MF, C_BT>(fr, v, A);
+    ctr<n, T, MF, C_DT>(fr, v, w);
+    ctr<n, T, MF, C_BT>(fr, w, by);
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = s2[a + SY * m + SZ * b];
+    ctr<n, T, MF, C_BT>(fr, v, w);
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      s[a + SY * l + SZ * b] = A[l];
+      s2[a + SY * l + SZ * b] = w[l];
+    }
+    wave_sync();
+    // x-line (., a, b) with a the y node and b the z node: u_x and u_z
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
+    ctr<n, T, MF, C_DT>(fr, v, w);
+    ctr<n, T, MF, C_BT>(fr, w, v);
+#pragma unroll
+    for (int q = 0; q < n; ++q) sink(0, q, a, b, v[q]);
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = s2[m + SY * a + SZ * b];
+    ctr<n, T, MF, C_BT>(fr, v, w);
+#pragma unroll
+    for (int q = 0; q < n; ++q) sink(2, q, a, b, w[q]);
+    wave_sync();
+    // u_y from the y-line result kept in registers
+#pragma unroll
+    for (int l = 0; l < n; ++l) s[a + SY * l + SZ * b] = by[l];
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = s[m + SY * a + SZ * b];
+    ctr<n, T, MF, C_BT>(fr, v, w);
+#pragma unroll
+    for (int q = 0; q < n; ++q) sink(1, q, a, b, w[q]);
+    wave_sync();
+    return;
+  }
+
   T S[NC][3][n];  // z-line role: gradients, then stresses, at (a, b, q)
   T bq[n];
   const T* cq = in.cq;  // coefficient at (a, b, q)
@@ -450,7 +598,7 @@ __device__ inline void element_op(const bool valid, const int e, const int k, co
 #pragma unroll
         for (int ii = 0; ii < n; ++ii)
           acc += Lg<n, T>(ma, ii) * Lg<n, T>(mb, jj) * s[ii + SY * jj + SZ * mc];
-      pout[(size_t)e * NP + r] = acc;
+      psink((size_t)e * NP + r, acc);
     }
     wave_sync();
   }
@@ -527,11 +675,35 @@ __device__ inline void element_op(const bool valid, const int e, const int k, co
   }
 }
 
-// Divergence only (no scatter): element-parallel, writes the pressure modes.
-template <int n, typename T, int F, int MF>
+// What happens to a finished output value v of index j (see Epi in kernels.h); the mode is
+// a template constant, so a plain store carries none of the epilogue's arguments.
+template <int EP, typename T>
+__device__ __forceinline__ void emit(const Epi<T>& e, const size_t j, const T v, T* __restrict__ y,
+                                     const int add) {
+  if constexpr (EP == EPI_RESID) {
+    e.r[j] = e.b[j] - v;
+  } else if constexpr (EP == EPI_CHEB_FIRST) {
+    const T ri = e.b[j] - v;
+    e.r[j] = ri;
+    e.dnew[j] = e.alpha * e.dinv[j] * ri;
+  } else if constexpr (EP == EPI_CHEB_STEP) {
+    const T ri = e.r[j] - v;
+    e.r[j] = ri;
+    const T d0 = e.dold[j];
+    const T dn = e.alpha * d0 + e.beta * e.dinv[j] * ri;
+    e.dnew[j] = dn;
+    e.x[j] += e.add_old ? d0 + dn : dn;
+  } else {
+    y[j] = add ? y[j] + v : v;
+  }
+}
+
+// Divergence only (no scatter): element-parallel, the pressure modes go through the epilogue.
+template <int n, typename T, int F, int MF, int EP>
 __global__ void __launch_bounds__(256)
 k_op_gather(const int N, const int k, const int M, const int E, const int nn, const T hh,
-            const T* __restrict__ u, T* __restrict__ pout, const T* __restrict__ sin_) {
+            const T* __restrict__ u, T* __restrict__ pout, const T* __restrict__ sin_,
+            const int add, const Epi<T> ep) {
   constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n, sizeof(T)>::SL;
   __shared__ T sm[2 * (SLOTS + 1) * SL];
   int slot, r;
@@ -549,8 +721,9 @@ k_op_gather(const int N, const int k, const int M, const int E, const int nn, co
   T* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
   ElemIn<n, 3, T> in;
   element_load<n, 3, T, F>(valid, e, ex, ey, ez, k, M, nn, u, nullptr, sin_, r, in);
-  element_op<n, 3, T, F, MF>(valid, e, k, hh, in, nullptr, pout, s0, s0 + (SLOTS + 1) * SL, r,
-                             [](int, int, int, int, T) {});
+  element_op<n, 3, T, F, MF>(valid, e, k, hh, in, nullptr,
+                             [&](size_t j, T v) { emit<EP>(ep, j, v, pout, add); }, s0,
+                             s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
 }
 
 // Brick geometry of the scatter kernel: a block owns a BX x BY tile of elements and marches
@@ -610,29 +783,6 @@ inline BrickDev brick_dev(const BrickGeom& g) {
   d.fz = (int)g.fz;
   d.per_comp = (int)g.per_comp;
   return d;
-}
-
-// What happens to a finished node value v of output index j (see Epi in kernels.h); the mode is
-// a template constant, so a plain store carries none of the epilogue's arguments.
-template <int EP, typename T>
-__device__ __forceinline__ void emit(const Epi<T>& e, const size_t j, const T v, T* __restrict__ y,
-                                     const int add) {
-  if constexpr (EP == EPI_RESID) {
-    e.r[j] = e.b[j] - v;
-  } else if constexpr (EP == EPI_CHEB_FIRST) {
-    const T ri = e.b[j] - v;
-    e.r[j] = ri;
-    e.dnew[j] = e.alpha * e.dinv[j] * ri;
-  } else if constexpr (EP == EPI_CHEB_STEP) {
-    const T ri = e.r[j] - v;
-    e.r[j] = ri;
-    const T d0 = e.dold[j];
-    const T dn = e.alpha * d0 + e.beta * e.dinv[j] * ri;
-    e.dnew[j] = dn;
-    e.x[j] += e.add_old ? d0 + dn : dn;
-  } else {
-    y[j] = add ? y[j] + v : v;
-  }
 }
 
 // Store one finished node value: direct when the node is owned by this brick alone, else into
@@ -735,7 +885,8 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
     // operator past 128 and costs a wave per SIMD: loads stay at the top of the layer)
     ElemIn<n, NC, T> in;
     element_load<n, NC, T, F>(valid, e, ex, ey, ez, k, M, G.nn, u, coef, sin_, r, in);
-    element_op<n, NC, T, F, MF>(valid, e, k, hh, in, pin, pout, s0, s0 + (SLOTS + 1) * SL, r,
+    element_op<n, NC, T, F, MF>(valid, e, k, hh, in, pin, [&](size_t j, T v) { pout[j] = v; }, s0,
+                                s0 + (SLOTS + 1) * SL, r,
                                 [&](int c, int x, int yy, int z, T v) {
                                   if (valid)
                                     atomicAdd(wbase + (c * (k + 1) + z) * WPS + yy * WXS + x, v);
@@ -876,8 +1027,8 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
   if constexpr ((F & (F_A | F_BT)) == 0) {
     constexpr int SLOTS = 4 * WaveMap<n>::EPW;
     ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
-    hipLaunchKernelGGL((k_op_gather<n, T, F, MF>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, N, k,
-                       M, E, nn, hh, u, pout, sin);
+    hipLaunchKernelGGL((k_op_gather<n, T, F, MF, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, N,
+                       k, M, E, nn, hh, u, pout, sin, (int)add, ep);
   } else {
     constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY;
     const BrickGeom G = brick_geom(N, k, BX, BY);
@@ -899,11 +1050,11 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
 }
 
 // Epilogues other than the plain store exist for the level operators (A with or without the
-// Dirichlet mask) only.
+// Dirichlet mask) and for the divergence alone (its pressure output: Chebyshev steps on K_w).
 template <int n, int NC, typename T, int F, int MF>
 void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, const T* pin, T* pout,
                const T* sin, bool add, void* work, const Epi<T>& ep) {
-  if constexpr (F == F_A || F == (F_A | F_DIR)) {
+  if constexpr (F == F_A || F == (F_A | F_DIR) || F == (F_B | F_DIR)) {
     switch (ep.mode) {
       case EPI_RESID:
         return op_launch_ep<n, NC, T, F, MF, EPI_RESID>(st, N, k, u, y, coef, pin, pout, sin, add,
@@ -1005,7 +1156,7 @@ k_elem_matrix(const int N, const double hh, const double* __restrict__ coef, dou
       for (int l = 0; l < n; ++l)
         in.uz[c][l] = (!dead && c == d && a == jx && b == jy && l == jz) ? 1.0 : 0.0;
     double* out = ae + ((size_t)(valid ? e : 0) * ND + col) * ND;
-    element_op<n, NC, double, F_A, 0>(valid, e, 1, hh, in, nullptr, nullptr, s0,
+    element_op<n, NC, double, F_A, 0>(valid, e, 1, hh, in, nullptr, [](size_t, double) {}, s0,
                                       s0 + (SLOTS + 1) * SL, r,
                                       [&](int c, int x, int yy, int z, double v) {
                                         if (valid) out[(x + 2 * yy + 4 * z) * NC + c] = v;
@@ -1108,6 +1259,146 @@ k_stencil(const int M, const T* __restrict__ S, const T* __restrict__ u, T* __re
       }
   }
   emit<EP>(ep, (size_t)c * nn + i, acc, y, add);
+}
+
+// Coarse tail of a scalar (Neumann) V-cycle in one workgroup: Chebyshev-Jacobi smoothing on an
+// assembled Q1 level of at most TAIL_MAX nodes, residual, restriction (linear 2:1), the coarsest
+// dense solve, prolongation and post-smoothing, with every vector in LDS and thread t owning
+// node t (its 27 stencil entries held in registers).  The steps and their arithmetic are those of
+// the per-kernel path (k_cheb_first, k_stencil with its epilogues, k_lin21, k_dense).
+template <typename T>
+__device__ inline T tail_apply(const int M, const int t, const T (&sr)[27], const T* v) {
+  const int ix = t % M, iy = (t / M) % M, iz = t / (M * M);
+  T acc = T(0);
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    const bool in = ix + ox >= 0 && ix + ox < M && iy + oy >= 0 && iy + oy < M && iz + oz >= 0 &&
+                    iz + oz < M;
+    const T vj = v[in ? t + ox + M * (oy + M * oz) : t];
+    acc += in ? sr[o] * vj : T(0);
+  }
+  return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THREADS)
+k_vcycle_tail(const TailArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg) {
+  __shared__ T b[TAIL_MAX], x[TAIL_MAX], r[TAIL_MAX], dv[2][TAIL_MAX], bc[TAIL_MAX], xc[TAIL_MAX];
+  const int t = threadIdx.x, M = a.M, nn = M * M * M, Mc = a.Mc, nc = Mc * Mc * Mc;
+  const bool own = t < nn;
+  T sr[27];
+#pragma unroll
+  for (int o = 0; o < 27; ++o) sr[o] = own ? a.S[(size_t)o * nn + t] : T(0);
+  const T dinv = own ? a.dinv[t] : T(0);
+  // pre-smoothing from x = 0
+  int cur = 0;
+  if (own) {
+    const T bt = bg[t];
+    const T di = a.inv_theta * dinv * bt;
+    b[t] = bt;
+    r[t] = bt;
+    dv[0][t] = di;
+    x[t] = di;
+  }
+  __syncthreads();
+  for (int it = 1; it < a.deg; ++it) {
+    const T v = tail_apply<T>(M, own ? t : 0, sr, dv[cur]);
+    if (own) {
+      const T ri = r[t] - v;
+      const T dn = a.alpha[it] * dv[cur][t] + a.beta[it] * dinv * ri;
+      r[t] = ri;
+      dv[cur ^ 1][t] = dn;
+      x[t] += dn;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  // residual and restriction
+  {
+    const T v = tail_apply<T>(M, own ? t : 0, sr, x);
+    if (own) r[t] = b[t] - v;
+  }
+  __syncthreads();
+  if (t < nc) {
+    const int ox = t % Mc, oy = (t / Mc) % Mc, oz = t / (Mc * Mc);
+    int xs[3], ys[3], zs[3];
+    double wx[3], wy[3], wz[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int fx = 2 * ox + q - 1, fy = 2 * oy + q - 1, fz = 2 * oz + q - 1;
+      const double w = q == 1 ? 1.0 : 0.5;
+      wx[q] = (fx >= 0 && fx < M) ? w : 0.0;
+      wy[q] = (fy >= 0 && fy < M) ? w : 0.0;
+      wz[q] = (fz >= 0 && fz < M) ? w : 0.0;
+      xs[q] = min(max(fx, 0), M - 1);
+      ys[q] = min(max(fy, 0), M - 1);
+      zs[q] = min(max(fz, 0), M - 1);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int qz = 0; qz < 3; ++qz) {
+      double sz = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        sz += wy[q / 3] * wx[q % 3] * (double)r[xs[q % 3] + M * (ys[q / 3] + M * zs[qz])];
+      s += wz[qz] * sz;
+    }
+    bc[t] = (T)s;
+  }
+  __syncthreads();
+  // coarsest: xc[idx[row]] = sum_c G[row, c] bc[idx[c]], one wavefront per row
+  {
+    const int lane = t & 63, wave = t >> 6;
+    for (int row = wave; row < a.nd; row += TAIL_THREADS / 64) {
+      double s = 0.0;
+      for (int c = lane; c < a.nd; c += 64) s += a.G[(size_t)row * a.nd + c] * (double)bc[a.gidx[c]];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+      if (lane == 0) xc[a.gidx[row]] = (T)s;
+    }
+  }
+  __syncthreads();
+  // prolongation x += P xc
+  if (own) {
+    const int fx = t % M, fy = (t / M) % M, fz = t / (M * M);
+    const int x0 = fx >> 1, y0 = fy >> 1, z0 = fz >> 1;
+    const int xs[2] = {x0, x0 + (fx & 1)}, ys[2] = {y0, y0 + (fy & 1)}, zs[2] = {z0, z0 + (fz & 1)};
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (double)xc[xs[q & 1] + Mc * (ys[(q >> 1) & 1] + Mc * zs[q >> 2])];
+    const double a0 = 0.5 * (v[0] + v[1]), a1 = 0.5 * (v[2] + v[3]);
+    const double a2 = 0.5 * (v[4] + v[5]), a3 = 0.5 * (v[6] + v[7]);
+    x[t] = x[t] + (T)(0.5 * (0.5 * (a0 + a1) + 0.5 * (a2 + a3)));
+  }
+  __syncthreads();
+  // post-smoothing from x: the first correction is added to x by the next step
+  cur = 0;
+  {
+    const T v = tail_apply<T>(M, own ? t : 0, sr, x);
+    if (own) {
+      const T ri = b[t] - v;
+      r[t] = ri;
+      dv[0][t] = a.inv_theta * dinv * ri;
+    }
+  }
+  __syncthreads();
+  bool pending = true;
+  for (int it = 1; it < a.deg; ++it) {
+    const T v = tail_apply<T>(M, own ? t : 0, sr, dv[cur]);
+    if (own) {
+      const T ri = r[t] - v;
+      const T d0 = dv[cur][t];
+      const T dn = a.alpha[it] * d0 + a.beta[it] * dinv * ri;
+      r[t] = ri;
+      dv[cur ^ 1][t] = dn;
+      x[t] += pending ? d0 + dn : dn;
+    }
+    __syncthreads();
+    cur ^= 1;
+    pending = false;
+  }
+  if (own) xg[t] = pending ? x[t] + dv[cur][t] : x[t];
 }
 
 template <int NC, typename T, int EP>
@@ -1508,17 +1799,6 @@ __global__ void k_cheb_first(size_t n, const T* __restrict__ b, const T* __restr
   x[i] = xzero ? di : x[i] + di;
 }
 template <typename T>
-__global__ void k_cheb_step(size_t n, const T* __restrict__ t, const T* __restrict__ dinv, T alpha,
-                            T beta, T* __restrict__ d, T* __restrict__ x, T* __restrict__ r) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const T ri = r[i] - t[i];
-  const T di = alpha * d[i] + beta * dinv[i] * ri;
-  r[i] = ri;
-  d[i] = di;
-  x[i] += di;
-}
-template <typename T>
 __global__ void k_scal(size_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = a * x[i];
@@ -1771,6 +2051,20 @@ template void launch_stencil_epi<double>(hipStream_t, int, int, const double*, c
 template void launch_stencil_epi<float>(hipStream_t, int, int, const float*, const float*, float*,
                                         bool, const Epi<float>&);
 
+template <typename T>
+void launch_vcycle_tail(hipStream_t st, const TailArgs<T>& a, const T* b, T* x) {
+  WB_REQUIRE(a.M >= 2 && a.M * a.M * a.M <= TAIL_MAX && 2 * a.Mc - 1 == a.M, WB_EINVAL,
+             "vcycle tail: level sizes out of range");
+  WB_REQUIRE(a.nd == a.Mc * a.Mc * a.Mc, WB_EINVAL, "vcycle tail: coarsest must be dense over all nodes");
+  WB_REQUIRE(a.deg >= 1 && a.deg <= TAIL_MAXDEG, WB_EINVAL, "vcycle tail: Chebyshev degree out of range");
+  char key[64];
+  snprintf(key, sizeof(key), "vcycle tail M=%d %s", a.M, sizeof(T) == 8 ? "f64" : "f32");
+  ProfScope ps(st, key);
+  hipLaunchKernelGGL((k_vcycle_tail<T>), dim3(1), dim3(TAIL_THREADS), 0, st, a, b, x);
+}
+template void launch_vcycle_tail<double>(hipStream_t, const TailArgs<double>&, const double*, double*);
+template void launch_vcycle_tail<float>(hipStream_t, const TailArgs<float>&, const float*, float*);
+
 #define WB_BY_ORDER(k, ...)                                       \
   switch ((k) + 1) {                                              \
     case 2: { constexpr int n = 2; __VA_ARGS__; } break;          \
@@ -1939,12 +2233,6 @@ void launch_cheb_first(hipStream_t st, size_t n, const T* b, const T* t, const T
                      inv_theta, d, x, r, (int)xzero);
 }
 template <typename T>
-void launch_cheb_step(hipStream_t st, size_t n, const T* t, const T* dinv, T alpha, T beta, T* d,
-                      T* x, T* r) {
-  hipLaunchKernelGGL((k_cheb_step<T>), dim3(grid_for(n, 256)), dim3(256), 0, st, n, t, dinv, alpha,
-                     beta, d, x, r);
-}
-template <typename T>
 void launch_sub(hipStream_t st, size_t n, const T* b, const T* t, T* r) {
   hipLaunchKernelGGL((k_sub<T>), dim3(grid_for(n, 256)), dim3(256), 0, st, n, b, t, r);
 }
@@ -1982,7 +2270,6 @@ void launch_remove_mean(hipStream_t st, int E, int np, T* p, double* partial, do
   template void launch_scale_nodes<T>(hipStream_t, int, int, const T*, const T*, T*);             \
   template void launch_cheb_first<T>(hipStream_t, size_t, const T*, const T*, const T*, T, T*, T*, \
                                      T*, bool);                                                    \
-  template void launch_cheb_step<T>(hipStream_t, size_t, const T*, const T*, T, T, T*, T*, T*);   \
   template void launch_sub<T>(hipStream_t, size_t, const T*, const T*, T*);                       \
   template void launch_mul<T>(hipStream_t, size_t, const T*, const T*, T*);                       \
   template void launch_scal<T>(hipStream_t, size_t, T, const T*, T*);                             \

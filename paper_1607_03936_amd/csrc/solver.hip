@@ -358,26 +358,6 @@ void cheb_level(Solver& s, Level<T>& L, const T* b, T* x, bool xzero) {
   if (pending) launch_axpby<T>(st, L.len, T(1), d0, T(1), x);
 }
 
-// Chebyshev-accelerated Jacobi (degree steps) for A x = b, A given as a callback.
-template <typename T, typename Op>
-void chebyshev(hipStream_t st, const Op& op, size_t len, const T* dinv, double lmin, double lmax,
-               int degree, const T* b, T* x, bool xzero, T* r, T* d, T* t) {
-  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-  double rho = 1.0 / sigma;
-  if (xzero) {
-    launch_cheb_first<T>(st, len, b, nullptr, dinv, (T)(1.0 / theta), d, x, r, true);
-  } else {
-    op(x, t);
-    launch_cheb_first<T>(st, len, b, t, dinv, (T)(1.0 / theta), d, x, r, false);
-  }
-  for (int s = 1; s < degree; ++s) {
-    op(d, t);
-    const double rho_new = 1.0 / (2.0 * sigma - rho);
-    launch_cheb_step<T>(st, len, t, dinv, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), d, x, r);
-    rho = rho_new;
-  }
-}
-
 // Largest eigenvalue of D^-1 A from `steps` Jacobi-CG steps started from r (device, overwritten);
 // the CG scalars stay in device memory, one host read at the end.
 template <typename Op>
@@ -653,6 +633,38 @@ void learned_step(Solver& s, Level<T>& L, const T* b, T* x) {
   launch_net_guarded_update<T>(st, L.len, s.red_out + 9, x, L.d, s.learned->counters);
 }
 
+// The last smoothed level of a scalar hierarchy and the coarsest solve run as one workgroup when
+// the level is an assembled Q1 level small enough for it (see launch_vcycle_tail).
+template <typename T>
+bool vcycle_tail(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
+  const Level<T>& L = H.L[li];
+  if (li + 2 != (int)H.L.size() || !L.S || L.NC != 1 || L.dir || !L.R.lin21) return false;
+  const Level<T>& C = H.L[li + 1];
+  const int M = L.N + 1, Mc = C.N + 1;
+  if (M * M * M > TAIL_MAX || H.nd != Mc * Mc * Mc || s.o.cheb_degree > TAIL_MAXDEG) return false;
+  TailArgs<T> a;
+  a.M = M;
+  a.Mc = Mc;
+  a.nd = H.nd;
+  a.deg = s.o.cheb_degree;
+  a.S = L.S;
+  a.dinv = L.dinv;
+  a.G = H.G;
+  a.gidx = H.gidx;
+  const double theta = 0.5 * (L.lmax + L.lmin), delta = 0.5 * (L.lmax - L.lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  a.inv_theta = (T)(1.0 / theta);
+  for (int it = 1; it < a.deg; ++it) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    a.alpha[it] = (T)(rho_new * rho);
+    a.beta[it] = (T)(2.0 * rho_new / delta);
+    rho = rho_new;
+  }
+  launch_vcycle_tail<T>(s.st, a, b, x);
+  return true;
+}
+
 template <typename T>
 void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
   hipStream_t st = s.st;
@@ -662,6 +674,7 @@ void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
     launch_dense<T>(st, H.nd, H.G, H.gidx, b, x);
     return;
   }
+  if (vcycle_tail<T>(s, H, li, b, x)) return;
   cheb_level<T>(s, L, b, x, true);
   Epi<T> res;  // r = b - A x
   res.mode = EPI_RESID;
@@ -693,25 +706,79 @@ void apply_K(Solver& s, Precond<T>& P, int side, const T* p, T* y) {
                nullptr);
 }
 
+// K_w p with an epilogue on the divergence kernel's output (see Epi).
+template <typename T>
+void apply_K_epi(Solver& s, Precond<T>& P, int side, const T* p, const Epi<T>& e) {
+  hipStream_t st = s.st;
+  const Mesh& m = s.m;
+  launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr,
+               nullptr, false, s.opwork);
+  launch_op_epi<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr,
+                   nullptr, P.winv[side], false, nullptr, e);
+}
+
+// Chebyshev-Jacobi on K_w (degree steps, diagonal dk), the updates fused into the divergence
+// kernel as in cheb_level; directions alternate between P.pd and P.pt, residual in P.pr.
+template <typename T>
+void cheb_K(Solver& s, Precond<T>& P, int side, const T* b, T* x, bool xzero) {
+  hipStream_t st = s.st;
+  const size_t pl = (size_t)s.m.E * s.m.np;
+  const double lmin = P.klmin[side], lmax = P.klmax[side];
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  T* d0 = P.pd;
+  T* d1 = P.pt;
+  bool pending = false;
+  if (xzero) {
+    launch_cheb_first<T>(st, pl, b, nullptr, P.dk[side], (T)(1.0 / theta), d0, x, P.pr, true);
+  } else {
+    Epi<T> e;
+    e.mode = EPI_CHEB_FIRST;
+    e.b = b;
+    e.r = P.pr;
+    e.dnew = d0;
+    e.dinv = P.dk[side];
+    e.alpha = (T)(1.0 / theta);
+    apply_K_epi<T>(s, P, side, x, e);
+    pending = true;
+  }
+  for (int it = 1; it < s.o.cheb_degree; ++it) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    Epi<T> e;
+    e.mode = EPI_CHEB_STEP;
+    e.add_old = pending ? 1 : 0;
+    e.r = P.pr;
+    e.dold = d0;
+    e.dnew = d1;
+    e.x = x;
+    e.dinv = P.dk[side];
+    e.alpha = (T)(rho_new * rho);
+    e.beta = (T)(2.0 * rho_new / delta);
+    apply_K_epi<T>(s, P, side, d0, e);
+    std::swap(d0, d1);
+    pending = false;
+    rho = rho_new;
+  }
+  if (pending) launch_axpby<T>(st, pl, T(1), d0, T(1), x);
+}
+
 template <typename T>
 void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* b, T* x) {
   hipStream_t st = s.st;
   const Mesh& m = s.m;
-  const size_t pl = (size_t)m.E * m.np;
-  auto op = [&](const T* in, T* out) { apply_K<T>(s, P, side, in, out); };
-  const int deg = s.o.cheb_degree;
-  chebyshev<T>(st, op, pl, P.dk[side], P.klmin[side], P.klmax[side], deg, b, x, true, P.pr, P.pd,
-               P.pt);
-  op(x, P.pt);
-  launch_sub<T>(st, pl, b, P.pt, P.pr);
+  cheb_K<T>(s, P, side, b, x, true);
+  Epi<T> res;  // r = b - K_w x
+  res.mode = EPI_RESID;
+  res.b = b;
+  res.r = P.pr;
+  apply_K_epi<T>(s, P, side, x, res);
   Hierarchy<T>& H = P.Pois[side];
   Level<T>& L0 = H.L[0];
   launch_fill<T>(st, L0.b, T(0), L0.len);
   launch_modal_IT<T>(st, m.N, m.k, P.pr, L0.b);
   vcycle<T>(s, H, 0, L0.b, L0.x);
   launch_modal_I<T>(st, m.N, m.k, L0.x, x, true);
-  chebyshev<T>(st, op, pl, P.dk[side], P.klmin[side], P.klmax[side], deg, b, x, false, P.pr, P.pd,
-               P.pt);
+  cheb_K<T>(s, P, side, b, x, false);
   launch_remove_mean<T>(st, m.E, m.np, x, s.red_partial, s.red_out + 1);
 }
 
