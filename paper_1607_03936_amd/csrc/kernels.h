@@ -35,14 +35,17 @@ size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size);
 //                                                                 x += dnew is left to the next)
 //   EPI_CHEB_STEP   r_j -= v, dnew_j = alpha dold_j + beta dinv_j r_j, x_j += dnew_j
 //                   (+ dold_j when add_old: the deferred first correction)
+//   EPI_CHEB_ZERO   the first two Chebyshev steps from x0 = 0 in one apply: the operator's
+//                   input is d0 = gamma dinv b, formed as it is read (u is not used), then
+//                   r_j = b_j - v, dnew_j = alpha d0_j + beta dinv_j r_j, x_j = d0_j + dnew_j
 // Buffers written by an epilogue must not be read by the same operator (its input is dold or
 // x for EPI_CHEB_STEP / EPI_RESID, so dnew != dold).
-enum : int { EPI_STORE = 0, EPI_RESID = 1, EPI_CHEB_FIRST = 2, EPI_CHEB_STEP = 3 };
+enum : int { EPI_STORE = 0, EPI_RESID = 1, EPI_CHEB_FIRST = 2, EPI_CHEB_STEP = 3, EPI_CHEB_ZERO = 4 };
 template <typename T>
 struct Epi {
   int mode = EPI_STORE;
   int add_old = 0;
-  T alpha = T(0), beta = T(0);
+  T alpha = T(0), beta = T(0), gamma = T(0);
   T* r = nullptr;
   const T* dold = nullptr;
   T* dnew = nullptr;
@@ -185,12 +188,13 @@ void launch_remove_global_mean(hipStream_t st, size_t n, double* x, double* part
 template <typename T>
 void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partial, double* out);
 constexpr int RED_BLOCKS = 1024;
+constexpr int MDOT_BLOCKS = 1024;
 // Pressure mean of the constant mode: p[e*np] -= mean_e p[e*np].
 template <typename T>
 void launch_remove_mean(hipStream_t st, int E, int np, T* p, double* partial, double* scratch);
 
-// FGMRES helpers (FP64): h[v] = V[v] . w for v < nv (V rows of stride ld),
-// w -= sum_v h[v] V[v], x += sum_v y[v] Z[v].
+// FGMRES helpers (FP64): h[v] = V[v] . w for v < nv (V rows of stride ld; partial holds
+// MDOT_BLOCKS doubles per vector), w -= sum_v h[v] V[v], x += sum_v y[v] Z[v].
 void launch_mdot(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* w,
                  double* partial, double* h);
 void launch_gemv_sub(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* h,

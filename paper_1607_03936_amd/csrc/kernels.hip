@@ -292,11 +292,13 @@ struct ElemIn {
 
 // Loads of one element, issued up front from in-bounds addresses (index 0 for idle lanes);
 // masked values are selected away afterwards.
-template <int n, int NC, typename T, int F>
+// ZIN: the input is ugain uscale u entry by entry (the zero-start Chebyshev direction).
+template <int n, int NC, typename T, int F, bool ZIN = false>
 __device__ inline void element_load(const bool valid, const int e, const int ex, const int ey,
                                     const int ez, const int k, const int M, const int nn,
                                     const T* __restrict__ u, const T* __restrict__ coef,
-                                    const T* __restrict__ sin_, const int r, ElemIn<n, NC, T>& in) {
+                                    const T* __restrict__ sin_, const int r, ElemIn<n, NC, T>& in,
+                                    const T* __restrict__ uscale = nullptr, const T ugain = T(0)) {
   constexpr int NN = n * n, N3 = n * n * n;
   if constexpr ((F & (F_A | F_B)) != 0) {
     const int a = r % n, b = r / n;
@@ -314,7 +316,11 @@ __device__ inline void element_load(const bool valid, const int e, const int ex,
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int l = 0; l < n; ++l) in.uz[c][l] = u[(size_t)c * nn + gidx[l]];
+      for (int l = 0; l < n; ++l) {
+        const size_t j = (size_t)c * nn + gidx[l];
+        if constexpr (ZIN) in.uz[c][l] = ugain * uscale[j] * u[j];
+        else in.uz[c][l] = u[j];
+      }
     if constexpr ((F & F_A) != 0) {
       const size_t eb = (size_t)(valid ? e : 0) * N3 + b * n + a;
 #pragma unroll
@@ -686,6 +692,13 @@ __device__ __forceinline__ void emit(const Epi<T>& e, const size_t j, const T v,
     const T ri = e.b[j] - v;
     e.r[j] = ri;
     e.dnew[j] = e.alpha * e.dinv[j] * ri;
+  } else if constexpr (EP == EPI_CHEB_ZERO) {
+    const T d0 = e.gamma * e.dinv[j] * e.b[j];
+    const T ri = e.b[j] - v;
+    e.r[j] = ri;
+    const T dn = e.alpha * d0 + e.beta * e.dinv[j] * ri;
+    e.dnew[j] = dn;
+    e.x[j] = d0 + dn;
   } else if constexpr (EP == EPI_CHEB_STEP) {
     const T ri = e.r[j] - v;
     e.r[j] = ri;
@@ -884,7 +897,11 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
     // (loading the next layer before the plane flush raises the register peak of the Q3
     // operator past 128 and costs a wave per SIMD: loads stay at the top of the layer)
     ElemIn<n, NC, T> in;
-    element_load<n, NC, T, F>(valid, e, ex, ey, ez, k, M, G.nn, u, coef, sin_, r, in);
+    if constexpr (EP == EPI_CHEB_ZERO)
+      element_load<n, NC, T, F, true>(valid, e, ex, ey, ez, k, M, G.nn, ep.b, coef, sin_, r, in,
+                                      ep.dinv, ep.gamma);
+    else
+      element_load<n, NC, T, F>(valid, e, ex, ey, ez, k, M, G.nn, u, coef, sin_, r, in);
     element_op<n, NC, T, F, MF>(valid, e, k, hh, in, pin, [&](size_t j, T v) { pout[j] = v; }, s0,
                                 s0 + (SLOTS + 1) * SL, r,
                                 [&](int c, int x, int yy, int z, T v) {
@@ -1062,6 +1079,11 @@ void op_launch(hipStream_t st, int N, int k, const T* u, T* y, const T* coef, co
       case EPI_CHEB_FIRST:
         return op_launch_ep<n, NC, T, F, MF, EPI_CHEB_FIRST>(st, N, k, u, y, coef, pin, pout, sin,
                                                              add, work, ep);
+      case EPI_CHEB_ZERO:
+        if constexpr ((F & F_A) != 0)
+          return op_launch_ep<n, NC, T, F, MF, EPI_CHEB_ZERO>(st, N, k, u, y, coef, pin, pout, sin,
+                                                              add, work, ep);
+        break;
       case EPI_CHEB_STEP:
         return op_launch_ep<n, NC, T, F, MF, EPI_CHEB_STEP>(st, N, k, u, y, coef, pin, pout, sin,
                                                             add, work, ep);
@@ -1244,8 +1266,10 @@ k_stencil(const int M, const T* __restrict__ S, const T* __restrict__ u, T* __re
         const int j = in ? i + (ox - 1) + M * ((oy - 1) + M * (oz - 1)) : i;
 #pragma unroll
         for (int d = 0; d < NC; ++d) {
+          const size_t jd = (size_t)d * nn + j;
           sv[p][d] = S[((size_t)(o * NC + c) * NC + d) * nn + i];
-          uv[p][d] = u[(size_t)d * nn + j];
+          if constexpr (EP == EPI_CHEB_ZERO) uv[p][d] = ep.gamma * ep.dinv[jd] * ep.b[jd];
+          else uv[p][d] = u[jd];
         }
       }
 #pragma unroll
@@ -1419,6 +1443,7 @@ void stencil_dispatch(hipStream_t st, int N, const T* S, const T* u, T* y, bool 
     case EPI_RESID: return stencil_launch<NC, T, EPI_RESID>(st, N, S, u, y, add, ep);
     case EPI_CHEB_FIRST: return stencil_launch<NC, T, EPI_CHEB_FIRST>(st, N, S, u, y, add, ep);
     case EPI_CHEB_STEP: return stencil_launch<NC, T, EPI_CHEB_STEP>(st, N, S, u, y, add, ep);
+    case EPI_CHEB_ZERO: return stencil_launch<NC, T, EPI_CHEB_ZERO>(st, N, S, u, y, add, ep);
     default: throw Error{WB_EINVAL, "unknown epilogue"};
   }
 }
@@ -1885,7 +1910,16 @@ __global__ void __launch_bounds__(256) k_mdot_partial(size_t n, int nv, const do
 #pragma unroll
   for (int j = 0; j < MDOT_VG; ++j) acc[j] = 0.0;
   const double* Vb = V + (size_t)v0 * ld;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  // two rows per pass: twice the loads in flight
+  for (; i + stride < n; i += 2 * stride) {
+    const double w0 = w[i], w1 = w[i + stride];
+#pragma unroll
+    for (int j = 0; j < MDOT_VG; ++j)
+      if (j < cnt) acc[j] += Vb[(size_t)j * ld + i] * w0 + Vb[(size_t)j * ld + i + stride] * w1;
+  }
+  if (i < n) {
     const double wi = w[i];
 #pragma unroll
     for (int j = 0; j < MDOT_VG; ++j)
@@ -2285,8 +2319,8 @@ template void launch_cast<double, double>(hipStream_t, size_t, const double*, do
 
 void launch_mdot(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* w,
                  double* partial, double* h) {
-  // nb <= 256 row blocks (the partial buffer holds 256 per vector), about 4 rows per thread
-  const int nb = (int)std::min<size_t>(256, std::max<size_t>(1, grid_for(n, 1024)));
+  // up to MDOT_BLOCKS row blocks, at least about 4 rows per thread
+  const int nb = (int)std::min<size_t>(MDOT_BLOCKS, std::max<size_t>(1, grid_for(n, 1024)));
   const int ng = (nv + MDOT_VG - 1) / MDOT_VG;
   hipLaunchKernelGGL(k_mdot_partial, dim3(nb, ng), dim3(256), 0, st, n, nv, V, ld, w, partial);
   hipLaunchKernelGGL(k_rows_sum, dim3(nv), dim3(256), 0, st, nb, partial, h);

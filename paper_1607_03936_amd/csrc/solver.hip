@@ -325,7 +325,25 @@ void cheb_level(Solver& s, Level<T>& L, const T* b, T* x, bool xzero) {
   T* d0 = L.d;
   T* d1 = L.t;
   bool pending = false;
-  if (xzero) {
+  int it = 1;
+  if (xzero && s.o.cheb_degree >= 2) {
+    // the first two steps in one operator apply (EPI_CHEB_ZERO): d0 is formed as it is read
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    Epi<T> e;
+    e.mode = EPI_CHEB_ZERO;
+    e.b = b;
+    e.r = L.r;
+    e.dnew = d1;
+    e.x = x;
+    e.dinv = L.dinv;
+    e.gamma = (T)(1.0 / theta);
+    e.alpha = (T)(rho_new * rho);
+    e.beta = (T)(2.0 * rho_new / delta);
+    level_op_epi<T>(s, L, nullptr, e);
+    std::swap(d0, d1);
+    rho = rho_new;
+    it = 2;
+  } else if (xzero) {
     launch_cheb_first<T>(st, L.len, b, nullptr, L.dinv, (T)(1.0 / theta), d0, x, L.r, true);
   } else {
     Epi<T> e;
@@ -338,7 +356,7 @@ void cheb_level(Solver& s, Level<T>& L, const T* b, T* x, bool xzero) {
     level_op_epi<T>(s, L, x, e);
     pending = true;
   }
-  for (int it = 1; it < s.o.cheb_degree; ++it) {
+  for (; it < s.o.cheb_degree; ++it) {
     const double rho_new = 1.0 / (2.0 * sigma - rho);
     Epi<T> e;
     e.mode = EPI_CHEB_STEP;
@@ -984,7 +1002,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.bvec = ar.alloc<double>(s.n_tot);
   s.xvec = ar.alloc<double>(s.n_tot);
   s.hbuf = ar.alloc<double>((size_t)3 * (R + 2));
-  s.mpartial = ar.alloc<double>((size_t)256 * (R + 2));
+  s.mpartial = ar.alloc<double>((size_t)MDOT_BLOCKS * (R + 2));
   clk.mark("Krylov space");
   WB_HIP(hipStreamSynchronize(st));
   s.t_setup = now_s() - t0;
