@@ -29,7 +29,7 @@ METRIC = "A(μ)-apply GDoF/s + %HBM peak; Stokes solve s to 1e-6, FP64 vs mixed/
 HBM_PEAK_GBS = 8000.0
 
 # bounded CPU-oracle samples: same parameters, smaller mesh, full solve when it converges
-CPU_SAMPLE = {"c1": 4, "c2": 20, "c3": 4, "c4": 8, "c5": 4}
+CPU_SAMPLE = {"c1": 4, "c2": 24, "c3": 4, "c4": 8, "c5": 4}
 
 
 def log(*a):

@@ -184,11 +184,15 @@ void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int 
 // x -= mean(x) (two-stage sum, deterministic)
 void launch_remove_global_mean(hipStream_t st, size_t n, double* x, double* partial, double* scratch);
 
-// Reductions into a device FP64 scalar (two stages, deterministic).
+// Reductions into a device FP64 scalar (block partials summed in block order, deterministic).
+// partial: at least RED_BLOCKS + 1 doubles; launch_remove_mean finishes its sum in the last
+// block to complete and uses partial[RED_BLOCKS] as a completion counter, which must be zero
+// before the first call (it is left zero).
 template <typename T>
 void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partial, double* out);
 constexpr int RED_BLOCKS = 1024;
 constexpr int MDOT_BLOCKS = 1024;
+constexpr int RED_LAST_BLOCKS = 64;  // blocks of the single-launch reductions
 // Pressure mean of the constant mode: p[e*np] -= mean_e p[e*np].
 template <typename T>
 void launch_remove_mean(hipStream_t st, int E, int np, T* p, double* partial, double* scratch);

@@ -711,34 +711,6 @@ __device__ __forceinline__ void emit(const Epi<T>& e, const size_t j, const T v,
   }
 }
 
-// Divergence only (no scatter): element-parallel, the pressure modes go through the epilogue.
-template <int n, typename T, int F, int MF, int EP>
-__global__ void __launch_bounds__(256)
-k_op_gather(const int N, const int k, const int M, const int E, const int nn, const T hh,
-            const T* __restrict__ u, T* __restrict__ pout, const T* __restrict__ sin_,
-            const int add, const Epi<T> ep) {
-  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n, sizeof(T)>::SL;
-  __shared__ T sm[2 * (SLOTS + 1) * SL];
-  int slot, r;
-  bool lane_ok;
-  WaveMap<n>::map(threadIdx.x, slot, r, lane_ok);
-  const int e = blockIdx.x * SLOTS + slot;
-  const bool valid = lane_ok && e < E;
-  int ex = 0, ey = 0, ez = 0;
-  if (valid) {
-    ex = e % N;
-    const int q = e / N;
-    ey = q % N;
-    ez = q / N;
-  }
-  T* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
-  ElemIn<n, 3, T> in;
-  element_load<n, 3, T, F>(valid, e, ex, ey, ez, k, M, nn, u, nullptr, sin_, r, in);
-  element_op<n, 3, T, F, MF>(valid, e, k, hh, in, nullptr,
-                             [&](size_t j, T v) { emit<EP>(ep, j, v, pout, add); }, s0,
-                             s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
-}
-
 // Brick geometry of the scatter kernel: a block owns a BX x BY tile of elements and marches
 // through a chunk of Bz element layers in z.
 template <int n> struct Tile;
@@ -849,6 +821,34 @@ struct WinPad {
   static constexpr int WX = (n - 1) * Tile<n>::BX + 1, WY = (n - 1) * Tile<n>::BY + 1;
   static constexpr int WXS = WX, WPS = WX * WY;
 };
+
+// Divergence only (no scatter): element-parallel, the pressure modes go through the epilogue.
+template <int n, typename T, int F, int MF, int EP>
+__global__ void __launch_bounds__(256)
+k_op_gather(const int N, const int k, const int M, const int E, const int nn, const T hh,
+            const T* __restrict__ u, T* __restrict__ pout, const T* __restrict__ sin_,
+            const int add, const Epi<T> ep) {
+  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n, sizeof(T)>::SL;
+  __shared__ T sm[2 * (SLOTS + 1) * SL];
+  int slot, r;
+  bool lane_ok;
+  WaveMap<n>::map(threadIdx.x, slot, r, lane_ok);
+  const int e = blockIdx.x * SLOTS + slot;
+  const bool valid = lane_ok && e < E;
+  int ex = 0, ey = 0, ez = 0;
+  if (valid) {
+    ex = e % N;
+    const int q = e / N;
+    ey = q % N;
+    ez = q / N;
+  }
+  T* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
+  ElemIn<n, 3, T> in;
+  element_load<n, 3, T, F>(valid, e, ex, ey, ez, k, M, nn, u, nullptr, sin_, r, in);
+  element_op<n, 3, T, F, MF>(valid, e, k, hh, in, nullptr,
+                             [&](size_t j, T v) { emit<EP>(ep, j, v, pout, add); }, s0,
+                             s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
+}
 
 // Scatter operator: y = op(u) (or y += op(u)), F_B output as well when requested.
 template <int n>
@@ -1862,6 +1862,37 @@ __device__ inline double block_sum(double v) {
   return s;
 }
 
+__global__ void __launch_bounds__(256) k_final_sum(int nb, const double* __restrict__ partial,
+                                                   double* out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// Second stage of a block reduction inside the same launch: each block publishes its partial
+// (thread 0, value s), the block that completes the count sums all partials in block order
+// into *out and re-arms the counter (partial[RED_BLOCKS], zero between launches).
+__device__ inline void finish_by_last_block(double s, double* partial, double* out) {
+  __shared__ int last;
+  unsigned* count = reinterpret_cast<unsigned*>(partial + RED_BLOCKS);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s;
+    __threadfence();  // the partial is visible device-wide before the count says so
+    last = atomicAdd(count, 1u) == gridDim.x - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // and the partials of the other blocks are seen here
+  double t = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) t += partial[i];
+  t = block_sum(t);
+  if (threadIdx.x == 0) {
+    *out = t;
+    *count = 0u;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_dot_partial(size_t n, const T* __restrict__ x,
                                                      const T* __restrict__ y, double* partial) {
@@ -1872,22 +1903,13 @@ __global__ void __launch_bounds__(256) k_dot_partial(size_t n, const T* __restri
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(256) k_final_sum(int nb, const double* __restrict__ partial,
-                                                   double* out) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
-  s = block_sum(s);
-  if (threadIdx.x == 0) *out = s;
-}
-
 template <typename T>
-__global__ void __launch_bounds__(256) k_mode0_partial(int E, int np, const T* __restrict__ p,
-                                                       double* partial) {
+__global__ void __launch_bounds__(256) k_mode0_sum(int E, int np, const T* __restrict__ p,
+                                                   double* partial, double* out) {
   double s = 0.0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x)
     s += (double)p[(size_t)e * np];
-  s = block_sum(s);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  finish_by_last_block(block_sum(s), partial, out);
 }
 
 template <typename T>
@@ -2285,6 +2307,8 @@ void launch_mul(hipStream_t st, size_t n, const T* a, const T* b, T* c) {
 }
 template <typename T>
 void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partial, double* out) {
+  // two launches: the full-bandwidth partial pass, then one block (a single-launch form with a
+  // device-wide fence per block measured slower here)
   int nb = (int)std::min<size_t>(RED_BLOCKS, grid_for(n, 256));
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL((k_dot_partial<T>), dim3(nb), dim3(256), 0, st, n, x, y, partial);
@@ -2292,9 +2316,10 @@ void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partia
 }
 template <typename T>
 void launch_remove_mean(hipStream_t st, int E, int np, T* p, double* partial, double* scratch) {
-  int nb = (int)std::min<size_t>(RED_BLOCKS, grid_for(E, 256));
-  hipLaunchKernelGGL((k_mode0_partial<T>), dim3(nb), dim3(256), 0, st, E, np, p, partial);
-  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, st, nb, partial, scratch);
+  // one launch for the sum: few blocks, since each block's completion carries a device-wide fence
+  int nb = (int)std::min<size_t>(RED_LAST_BLOCKS, grid_for(E, 256));
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL((k_mode0_sum<T>), dim3(nb), dim3(256), 0, st, E, np, p, partial, scratch);
   hipLaunchKernelGGL((k_mode0_sub<T>), dim3(grid_for(E, 256)), dim3(256), 0, st, E, np, p, scratch);
 }
 

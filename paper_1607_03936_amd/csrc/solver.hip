@@ -718,10 +718,10 @@ template <typename T>
 void apply_K(Solver& s, Precond<T>& P, int side, const T* p, T* y) {
   hipStream_t st = s.st;
   const Mesh& m = s.m;
-  launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr, nullptr, false,
-               s.opwork);
-  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y, P.winv[side], false,
-               nullptr);
+  launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr,
+               nullptr, false, s.opwork);
+  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y,
+               P.winv[side], false, nullptr);
 }
 
 // K_w p with an epilogue on the divergence kernel's output (see Epi).
@@ -907,6 +907,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.st = st;
   Arena& ar = s.arena;
   s.red_partial = ar.alloc<double>(RED_BLOCKS * 128);
+  launch_fill<double>(st, s.red_partial, 0.0, (size_t)RED_BLOCKS * 128);  // the reduction counter
   s.red_out = ar.alloc<double>(16);
   s.lz = ar.alloc<double>(LZ_SLOTS);
   const int n3 = (m.k + 1) * (m.k + 1) * (m.k + 1);
