@@ -129,9 +129,9 @@ void launch_poisson_coef(hipStream_t st, int N, int k, double amp, const double*
 // Q2 -> Q1 p-step) or of its transpose; those transfers run in a kernel with the weights built in.
 struct Rows1D {
   int rows, cols, W;
-  int* cnt;
-  int* col;
-  double* val;
+  const int* cnt;
+  const int* col;
+  const double* val;
   int lin21;
 };
 template <typename T>
@@ -172,10 +172,11 @@ template <typename T> void launch_mul(hipStream_t st, size_t n, const T* a, cons
 // r = b - t
 template <typename T> void launch_sub(hipStream_t st, size_t n, const T* b, const T* t, T* r);
 
-// Jacobi-CG step halves with the scalars in device memory: r -= (rz/pq) q, z = dinv r; and
-// p = z + (rz_new/rz_old) p (non-positive denominators give a zero coefficient).
+// Jacobi-CG step halves with the scalars in device memory: r -= (rz/pq) q, z = dinv r, and
+// rz_new = r . z (partial: reduction scratch as for launch_dot); p = z + (rz_new/rz_old) p
+// (non-positive denominators give a zero coefficient).
 void launch_cg_r(hipStream_t st, size_t n, const double* q, const double* dinv, double* r, double* z,
-                 const double* rz, const double* pq);
+                 const double* rz, const double* pq, double* partial, double* rz_new);
 void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const double* rz_new,
                  const double* rz_old);
 // x_i = 2 U(splitmix64(seed * 2^32 + i)) - 1, zero on boundary nodes of an [NC][M^3] vector
@@ -185,9 +186,10 @@ void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int 
 void launch_remove_global_mean(hipStream_t st, size_t n, double* x, double* partial, double* scratch);
 
 // Reductions into a device FP64 scalar (block partials summed in block order, deterministic).
-// partial: at least RED_BLOCKS + 1 doubles; launch_remove_mean finishes its sum in the last
-// block to complete and uses partial[RED_BLOCKS] as a completion counter, which must be zero
-// before the first call (it is left zero).
+// partial: at least RED_BLOCKS + 1 doubles.  Reductions over at most RED_LAST_BLOCKS blocks
+// (launch_remove_mean always, launch_dot and launch_cg_r for n <= 256 RED_LAST_BLOCKS) finish in
+// the last block to complete, in one launch, and use partial[RED_BLOCKS] as a completion counter,
+// which must be zero before the first call (it is left zero); larger ones take a second launch.
 template <typename T>
 void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partial, double* out);
 constexpr int RED_BLOCKS = 1024;

@@ -1893,14 +1893,19 @@ __device__ inline void finish_by_last_block(double s, double* partial, double* o
   }
 }
 
-template <typename T>
+template <typename T, bool LAST>
 __global__ void __launch_bounds__(256) k_dot_partial(size_t n, const T* __restrict__ x,
-                                                     const T* __restrict__ y, double* partial) {
+                                                     const T* __restrict__ y, double* partial,
+                                                     double* out) {
   double s = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     s += (double)x[i] * (double)y[i];
   s = block_sum(s);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if constexpr (LAST) {
+    finish_by_last_block(s, partial, out);
+  } else {
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
 }
 
 template <typename T>
@@ -1983,15 +1988,28 @@ __global__ void k_gemv(size_t n, int nv, const double* __restrict__ V, size_t ld
 // Jacobi-CG steps with device scalars (eigenvalue estimate): alpha = rz / pq, r -= alpha q,
 // z = dinv r; then beta = rz_new / rz, p = z + beta p.  Non-positive denominators give 0 (the
 // host reads the scalars afterwards and stops the recurrence there).
-__global__ void k_cg_r(size_t n, const double* __restrict__ q, const double* __restrict__ dinv,
-                       double* __restrict__ r, double* __restrict__ z, const double* __restrict__ rz,
-                       const double* __restrict__ pq) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// (grid-stride; with LAST the block partials of r . z are finished by the last block, else
+// they are left in partial for k_final_sum)
+template <bool LAST>
+__global__ void __launch_bounds__(256)
+k_cg_r(size_t n, const double* __restrict__ q, const double* __restrict__ dinv,
+       double* __restrict__ r, double* __restrict__ z, const double* __restrict__ rz,
+       const double* __restrict__ pq, double* partial, double* rz_new) {
   const double a = (*pq > 0.0 && *rz > 0.0) ? *rz / *pq : 0.0;
-  const double ri = r[i] - a * q[i];
-  r[i] = ri;
-  z[i] = dinv[i] * ri;
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double ri = r[i] - a * q[i];
+    const double zi = dinv[i] * ri;
+    r[i] = ri;
+    z[i] = zi;
+    s += ri * zi;
+  }
+  s = block_sum(s);
+  if constexpr (LAST) {
+    finish_by_last_block(s, partial, rz_new);
+  } else {
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
 }
 __global__ void k_cg_p(size_t n, const double* __restrict__ z, double* __restrict__ p,
                        const double* __restrict__ rz_new, const double* __restrict__ rz_old) {
@@ -2307,11 +2325,15 @@ void launch_mul(hipStream_t st, size_t n, const T* a, const T* b, T* c) {
 }
 template <typename T>
 void launch_dot(hipStream_t st, size_t n, const T* x, const T* y, double* partial, double* out) {
-  // two launches: the full-bandwidth partial pass, then one block (a single-launch form with a
-  // device-wide fence per block measured slower here)
+  // short vectors: one launch finished by the last block; long ones: the full-bandwidth partial
+  // pass, then one block (a device-wide fence in each of many blocks measured slower)
   int nb = (int)std::min<size_t>(RED_BLOCKS, grid_for(n, 256));
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_dot_partial<T>), dim3(nb), dim3(256), 0, st, n, x, y, partial);
+  if (nb <= RED_LAST_BLOCKS) {
+    hipLaunchKernelGGL((k_dot_partial<T, true>), dim3(nb), dim3(256), 0, st, n, x, y, partial, out);
+    return;
+  }
+  hipLaunchKernelGGL((k_dot_partial<T, false>), dim3(nb), dim3(256), 0, st, n, x, y, partial, out);
   hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, st, nb, partial, out);
 }
 template <typename T>
@@ -2360,8 +2382,16 @@ void launch_gemv_add(hipStream_t st, size_t n, int nv, const double* Z, size_t l
 }
 
 void launch_cg_r(hipStream_t st, size_t n, const double* q, const double* dinv, double* r, double* z,
-                 const double* rz, const double* pq) {
-  hipLaunchKernelGGL(k_cg_r, dim3(grid_for(n, 256)), dim3(256), 0, st, n, q, dinv, r, z, rz, pq);
+                 const double* rz, const double* pq, double* partial, double* rz_new) {
+  const int nb = (int)std::max<size_t>(1, std::min<size_t>(RED_BLOCKS, grid_for(n, 256)));
+  if (nb <= RED_LAST_BLOCKS) {
+    hipLaunchKernelGGL((k_cg_r<true>), dim3(nb), dim3(256), 0, st, n, q, dinv, r, z, rz, pq, partial,
+                       rz_new);
+  } else {
+    hipLaunchKernelGGL((k_cg_r<false>), dim3(nb), dim3(256), 0, st, n, q, dinv, r, z, rz, pq,
+                       partial, rz_new);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, st, nb, partial, rz_new);
+  }
 }
 void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const double* rz_new,
                  const double* rz_old) {

@@ -46,7 +46,7 @@ struct Level {
   double lmin = 0, lmax = 0;
   T *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
   Rows1D P{}, R{};         // prolongation from / restriction to the next coarser level
-  double* Q = nullptr;     // coefficient coarsening matrix from the next finer level
+  const double* Q = nullptr;  // coefficient coarsening matrix from the next finer level
   T* S = nullptr;          // assembled 27-point stencil (Q1 levels within the size limit), else null
 };
 
@@ -63,7 +63,8 @@ struct Hierarchy {
 std::vector<std::pair<int, int>> level_schedule(int N, int k, int p_schedule);
 
 struct Solver;
-constexpr int LZ_SLOTS = 256;
+constexpr int LZ_SLOTS = 4096;     // device scalars of the eigenvalue estimates of one setup
+constexpr int AUX_STREAMS = 4;     // streams of the concurrent setup estimates
 
 // Preconditioner state in precision T (FP64 or FP32).
 template <typename T>
@@ -108,6 +109,13 @@ struct Solver {
   double* lz = nullptr;           // [LZ_SLOTS] Lanczos scalars
   double* ae = nullptr;           // element-matrix scratch of the Q1 assembly
   size_t ae_len = 0;
+  // setup: eigenvalue estimates of independent levels run concurrently on auxiliary streams,
+  // each with its own reduction scratch and face-array workspace
+  hipStream_t aux[AUX_STREAMS] = {};
+  hipEvent_t aux_ev[AUX_STREAMS] = {};
+  hipEvent_t main_ev = nullptr;
+  double* aux_partial[AUX_STREAMS] = {};
+  void* aux_work[AUX_STREAMS] = {};
   // Krylov space
   size_t n_tot = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hbuf = nullptr, *mpartial = nullptr;

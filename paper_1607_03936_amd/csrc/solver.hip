@@ -38,6 +38,34 @@ void mem_trim() {
   pool_trim_locked();
 }
 
+// Device copies of host-built constant tables (coefficient coarsening matrices, transfer rows,
+// the reference divergence).  They depend only on the mesh sizes and orders, so each content is
+// uploaded once per device and kept for the process (a few KB each): solver setup then issues no
+// blocking host-to-device copies for them.
+namespace {
+std::mutex g_tab_mu;
+std::map<std::string, void*> g_tab;
+}  // namespace
+
+const void* const_table(const void* host, size_t bytes) {
+  int dev = 0;
+  WB_HIP(hipGetDevice(&dev));
+  std::string key(reinterpret_cast<const char*>(&dev), sizeof(dev));
+  key.append(reinterpret_cast<const char*>(host), bytes);
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  auto it = g_tab.find(key);
+  if (it != g_tab.end()) return it->second;
+  void* d = nullptr;
+  WB_HIP(hipMalloc(&d, std::max<size_t>(bytes, 8)));
+  WB_HIP(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice));
+  g_tab.emplace(std::move(key), d);
+  return d;
+}
+template <typename T>
+const T* const_table(const std::vector<T>& v) {
+  return static_cast<const T*>(const_table(v.data(), sizeof(T) * v.size()));
+}
+
 Arena::~Arena() {
   if (ptrs_.empty()) return;
   // queued work on these blocks ends before they can be handed out again (hipFree waited too)
@@ -179,7 +207,7 @@ void splitmix_vector(unsigned long long seed, size_t n, std::vector<double>& out
 }
 
 // ---------------------------------------------------------------- 1D transfer tables
-Rows1D upload_rows(Arena& ar, const std::vector<std::vector<std::pair<int, double>>>& rows, int ncols) {
+Rows1D upload_rows(const std::vector<std::vector<std::pair<int, double>>>& rows, int ncols) {
   int W = 1;
   for (auto& r : rows) W = std::max<int>(W, (int)r.size());
   const int R = (int)rows.size();
@@ -197,17 +225,14 @@ Rows1D upload_rows(Arena& ar, const std::vector<std::vector<std::pair<int, doubl
   o.cols = ncols;
   o.W = W;
   o.lin21 = 0;
-  o.cnt = ar.alloc<int>(R);
-  o.col = ar.alloc<int>((size_t)R * W);
-  o.val = ar.alloc<double>((size_t)R * W);
-  WB_HIP(hipMemcpy(o.cnt, cnt.data(), sizeof(int) * R, hipMemcpyHostToDevice));
-  WB_HIP(hipMemcpy(o.col, col.data(), sizeof(int) * R * W, hipMemcpyHostToDevice));
-  WB_HIP(hipMemcpy(o.val, val.data(), sizeof(double) * R * W, hipMemcpyHostToDevice));
+  o.cnt = const_table(cnt);
+  o.col = const_table(col);
+  o.val = const_table(val);
   return o;
 }
 
 // P1[i_f][I_c]: coarse continuous 1D basis (Nc elements, order kc) at the fine nodes (Nf, kf).
-void make_transfer(Arena& ar, int Nc, int kc, int Nf, int kf, Rows1D& P, Rows1D& R) {
+void make_transfer(int Nc, int kc, int Nf, int kf, Rows1D& P, Rows1D& R) {
   const Tables& tf = tables(kf);
   const Tables& tc = tables(kc);
   const int Mf = kf * Nf + 1, Mc = kc * Nc + 1;
@@ -224,8 +249,8 @@ void make_transfer(Arena& ar, int Nc, int kc, int Nf, int kf, Rows1D& P, Rows1D&
   }
   for (int i = 0; i < Mf; ++i)
     for (auto& cv : prow[i]) rrow[cv.first].push_back({i, cv.second});
-  P = upload_rows(ar, prow, Mc);
-  R = upload_rows(ar, rrow, Mf);
+  P = upload_rows(prow, Mc);
+  R = upload_rows(rrow, Mf);
   bool lin = Mf == 2 * Mc - 1;
   for (int i = 0; lin && i < Mf; ++i) {
     const auto& r = prow[i];
@@ -376,29 +401,26 @@ void cheb_level(Solver& s, Level<T>& L, const T* b, T* x, bool xzero) {
   if (pending) launch_axpby<T>(st, L.len, T(1), d0, T(1), x);
 }
 
-// Largest eigenvalue of D^-1 A from `steps` Jacobi-CG steps started from r (device, overwritten);
-// the CG scalars stay in device memory, one host read at the end.
+// Largest eigenvalue of D^-1 A from `steps` Jacobi-CG steps started from r (device, overwritten).
+// The CG scalars stay in device memory, rz[0..steps] then pq[0..steps-1] at lz (2 steps + 1
+// doubles); lanczos_finish turns them into the estimate once they are on the host.
 template <typename Op>
-double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, int steps, double* r,
-                   double* z, double* p, double* q) {
-  hipStream_t st = s.st;
-  WB_REQUIRE(steps >= 1 && 2 * steps + 1 <= LZ_SLOTS, WB_EINVAL, "lanczos_steps out of range");
-  // device scalars: rz[0..steps] then pq[0..steps-1]
-  double* rz = s.lz;
-  double* pq = s.lz + steps + 1;
+void lanczos_enqueue(hipStream_t st, const Op& op, size_t len, const double* dinv, int steps,
+                     double* r, double* z, double* p, double* q, double* lz, double* partial) {
+  double* rz = lz;
+  double* pq = lz + steps + 1;
   launch_mul<double>(st, len, dinv, r, z);
   WB_HIP(hipMemcpyAsync(p, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
-  launch_dot<double>(st, len, r, z, s.red_partial, rz);
+  launch_dot<double>(st, len, r, z, partial, rz);
   for (int it = 0; it < steps; ++it) {
     op(p, q);
-    launch_dot<double>(st, len, p, q, s.red_partial, pq + it);
-    launch_cg_r(st, len, q, dinv, r, z, rz + it, pq + it);
-    launch_dot<double>(st, len, r, z, s.red_partial, rz + it + 1);
+    launch_dot<double>(st, len, p, q, partial, pq + it);
+    launch_cg_r(st, len, q, dinv, r, z, rz + it, pq + it, partial, rz + it + 1);
     launch_cg_p(st, len, z, p, rz + it + 1, rz + it);
   }
-  std::vector<double> h(2 * steps + 1);
-  WB_HIP(hipMemcpyAsync(h.data(), s.lz, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-  WB_HIP(hipStreamSynchronize(st));
+}
+
+double lanczos_finish(const double* h, int steps) {
   std::vector<double> alphas, betas;
   for (int it = 0; it < steps; ++it) {
     const double rzj = h[it], pqj = h[steps + 1 + it], rzn = h[it + 1];
@@ -419,21 +441,88 @@ double lanczos_max(Solver& s, const Op& op, size_t len, const double* dinv, int 
 
 // Chebyshev interval [0.1, 1.1] * lambda_max(D^-1 A) of a level, lambda_max from Jacobi-CG
 // (Lanczos) steps started from the splitmix64 vector of `seed` (Dirichlet entries zeroed, or
-// the mean removed for the Neumann Poisson levels).
-void set_cheb_bounds(Solver& s, Level<double>& L, unsigned long long seed) {
-  hipStream_t st = s.st;
+// the mean removed for the Neumann Poisson levels).  Enqueued on `st` with its own reduction
+// scratch `partial` (RED_BLOCKS + 64 doubles) and face workspace `work`; the level's work vectors
+// are zero again afterwards.
+void cheb_bounds_enqueue(Solver& s, Level<double>& L, unsigned long long seed, hipStream_t st,
+                         double* partial, void* work, double* lz) {
   const int M = L.k * L.N + 1;
   launch_splitmix_vec(st, L.len, seed, L.dir ? M : 0, L.x);
-  if (!L.dir) launch_remove_global_mean(st, L.len, L.x, s.red_partial, s.red_out + 12);
-  auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out, s.opwork); };
-  const double lam = lanczos_max(s, op, L.len, L.dinv, s.o.lanczos_steps, L.x, L.b, L.r, L.d);
-  L.lmin = 0.1 * lam;
-  L.lmax = 1.1 * lam;
+  if (!L.dir) launch_remove_global_mean(st, L.len, L.x, partial, partial + RED_BLOCKS + 32);
+  auto op = [&](const double* in, double* out) { level_op<double>(st, L, in, out, work); };
+  lanczos_enqueue(st, op, L.len, L.dinv, s.o.lanczos_steps, L.x, L.b, L.r, L.d, lz, partial);
   for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
 }
 
-// Build an FP64 hierarchy on `coef0` (velocity if NC == 3, Poisson if NC == 1).
-void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef0, int seed_base) {
+void set_bounds(Level<double>& L, double lam) {
+  L.lmin = 0.1 * lam;
+  L.lmax = 1.1 * lam;
+}
+
+// The same, finished at once (one host read).
+void set_cheb_bounds(Solver& s, Level<double>& L, unsigned long long seed) {
+  const int steps = s.o.lanczos_steps;
+  cheb_bounds_enqueue(s, L, seed, s.st, s.red_partial, s.opwork, s.lz);
+  std::vector<double> h(2 * steps + 1);
+  WB_HIP(hipMemcpyAsync(h.data(), s.lz, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s.st));
+  WB_HIP(hipStreamSynchronize(s.st));
+  set_bounds(L, lanczos_finish(h.data(), steps));
+}
+
+// Deferred eigenvalue estimates of a solver setup: each smoothed level's recurrence runs on one
+// of the auxiliary streams (round robin; the levels are independent and their launches small),
+// its scalars in its own slice of s.lz; finish_setup_estimates reads them all at once.
+struct SetupEstimates {
+  struct Job {
+    double* lmin;
+    double* lmax;
+    size_t slice;
+  };
+  std::vector<Job> jobs;
+  int next = 0;
+};
+
+size_t lz_slice(const Solver& s) { return (size_t)2 * s.o.lanczos_steps + 1; }
+
+double* next_lz(Solver& s, SetupEstimates& E, double* lmin, double* lmax) {
+  const size_t slice = E.jobs.size() * lz_slice(s);
+  WB_REQUIRE(slice + lz_slice(s) <= (size_t)LZ_SLOTS, WB_EINVAL, "lanczos_steps out of range");
+  E.jobs.push_back({lmin, lmax, slice});
+  return s.lz + slice;
+}
+
+void enqueue_level_bounds(Solver& s, SetupEstimates& E, Level<double>& L, unsigned long long seed) {
+  const int k = E.next++ % AUX_STREAMS;
+  WB_HIP(hipStreamWaitEvent(s.aux[k], s.main_ev, 0));
+  double* lz = next_lz(s, E, &L.lmin, &L.lmax);
+  cheb_bounds_enqueue(s, L, seed, s.aux[k], s.aux_partial[k], s.aux_work[k], lz);
+}
+
+// Joins the auxiliary streams into s.st and enqueues the read of every pending estimate into h.
+void join_setup_estimates(Solver& s, const SetupEstimates& E, std::vector<double>& h) {
+  for (int k = 0; k < AUX_STREAMS; ++k) {
+    WB_HIP(hipEventRecord(s.aux_ev[k], s.aux[k]));
+    WB_HIP(hipStreamWaitEvent(s.st, s.aux_ev[k], 0));
+  }
+  h.assign(E.jobs.size() * lz_slice(s), 0.0);
+  if (!h.empty())
+    WB_HIP(hipMemcpyAsync(h.data(), s.lz, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s.st));
+}
+
+// After the stream has been synchronized: the Chebyshev intervals from the estimates in h.
+void finish_setup_estimates(const Solver& s, const SetupEstimates& E, const std::vector<double>& h) {
+  for (const auto& j : E.jobs) {
+    const double lam = lanczos_finish(h.data() + j.slice, s.o.lanczos_steps);
+    *j.lmin = 0.1 * lam;
+    *j.lmax = 1.1 * lam;
+  }
+}
+
+// Build an FP64 hierarchy on `coef0` (velocity if NC == 3, Poisson if NC == 1).  The
+// eigenvalue estimates of its smoothed levels are enqueued into E; the coarsest inverse is
+// formed by coarsest_inverse once its stencil is on the host.
+void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef0, int seed_base,
+                     SetupEstimates& E) {
   hipStream_t st = s.st;
   Arena& ar = s.arena;
   auto sched = level_schedule(s.m.N, s.m.k, s.o.p_schedule);
@@ -456,14 +545,10 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     } else {
       const Level<double>& F = H.L[li - 1];
       if (F.N == L.N) {
-        auto Q = coarsen_matrix(F.k + 1, n, 1);
-        L.Q = ar.alloc<double>(Q.size());
-        WB_HIP(hipMemcpy(L.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
+        L.Q = const_table(coarsen_matrix(F.k + 1, n, 1));
         launch_coarsen_p(st, L.E, F.k + 1, n, L.Q, F.coef, L.coef);
       } else {
-        auto Q = coarsen_matrix(n, n, 2);
-        L.Q = ar.alloc<double>(Q.size());
-        WB_HIP(hipMemcpy(L.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
+        L.Q = const_table(coarsen_matrix(n, n, 2));
         launch_coarsen_h(st, F.N, n, L.Q, F.coef, L.coef);
       }
     }
@@ -481,12 +566,24 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     L.d = ar.alloc<double>(L.len);
     L.t = ar.alloc<double>(L.len);
     for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
-    if (li > 0) make_transfer(ar, L.N, L.k, H.L[li - 1].N, H.L[li - 1].k, H.L[li - 1].P, H.L[li - 1].R);
+    if (li > 0) make_transfer(L.N, L.k, H.L[li - 1].N, H.L[li - 1].k, H.L[li - 1].P, H.L[li - 1].R);
   }
   // Chebyshev bounds from the Lanczos estimate on every smoothed level
-  for (int li = 0; li + 1 < nl; ++li) set_cheb_bounds(s, H.L[li], (unsigned long long)(seed_base + li));
-  // coarsest: dense inverse (velocity: interior DOFs, SPD) or pseudo-inverse (Poisson, Neumann)
+  WB_HIP(hipEventRecord(s.main_ev, st));
+  for (int li = 0; li + 1 < nl; ++li)
+    enqueue_level_bounds(s, E, H.L[li], (unsigned long long)(seed_base + li));
   Level<double>& C = H.L[nl - 1];
+  WB_REQUIRE(C.S != nullptr, WB_EUNSUPPORTED, "coarsest level is not Q1");
+}
+
+// Coarsest level: dense inverse (velocity: interior DOFs, SPD) or pseudo-inverse (Poisson,
+// Neumann), from its stencil Sh (host copy).
+void coarsest_inverse(Solver& s, Hierarchy<double>& H, const std::vector<double>& Sh,
+                      std::vector<std::vector<double>>& keep_d, std::vector<std::vector<int>>& keep_i) {
+  hipStream_t st = s.st;
+  Arena& ar = s.arena;
+  Level<double>& C = H.L.back();
+  const int NC = C.NC;
   const int M = C.k * C.N + 1;
   std::vector<int> idx;
   for (size_t i = 0; i < C.len; ++i) {
@@ -496,11 +593,7 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
     if (!C.dir || !bnd) idx.push_back((int)i);
   }
   const int nd = (int)idx.size();
-  // the dense matrix from the coarsest level's stencil (one copy to the host)
-  WB_REQUIRE(C.S != nullptr, WB_EUNSUPPORTED, "coarsest level is not Q1");
-  std::vector<double> Sh(q1_stencil_len(NC, C.N)), Ad((size_t)nd * nd, 0.0);
-  WB_HIP(hipMemcpyAsync(Sh.data(), C.S, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost, st));
-  WB_HIP(hipStreamSynchronize(st));
+  std::vector<double> Ad((size_t)nd * nd, 0.0);
   std::vector<int> pos(C.len, -1);
   for (int i = 0; i < nd; ++i) pos[idx[i]] = i;
   for (int i = 0; i < nd; ++i) {
@@ -544,8 +637,12 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
   H.nd = nd;
   H.G = ar.alloc<double>((size_t)nd * nd);
   H.gidx = ar.alloc<int>(nd);
-  WB_HIP(hipMemcpy(H.G, Ad.data(), sizeof(double) * Ad.size(), hipMemcpyHostToDevice));
-  WB_HIP(hipMemcpy(H.gidx, idx.data(), sizeof(int) * nd, hipMemcpyHostToDevice));
+  // the host buffers stay alive (keep_*) until the caller has synchronized the stream
+  keep_d.push_back(std::move(Ad));
+  keep_i.push_back(std::move(idx));
+  WB_HIP(hipMemcpyAsync(H.G, keep_d.back().data(), sizeof(double) * keep_d.back().size(),
+                        hipMemcpyHostToDevice, st));
+  WB_HIP(hipMemcpyAsync(H.gidx, keep_i.back().data(), sizeof(int) * nd, hipMemcpyHostToDevice, st));
   launch_fill<double>(st, C.x, 0.0, C.len);
   launch_fill<double>(st, C.t, 0.0, C.len);
 }
@@ -869,6 +966,11 @@ void apply_precond_any(Solver& s, const double* ru, const double* rp, double* zu
 Solver::~Solver() {
   if (pgraph) (void)hipGraphExecDestroy(pgraph);
   if (cap_st) (void)hipStreamDestroy(cap_st);
+  for (int k = 0; k < AUX_STREAMS; ++k) {
+    if (aux_ev[k]) (void)hipEventDestroy(aux_ev[k]);
+    if (aux[k]) (void)hipStreamDestroy(aux[k]);
+  }
+  if (main_ev) (void)hipEventDestroy(main_ev);
 }
 
 namespace {
@@ -918,7 +1020,16 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
       wbytes = std::max(wbytes, op_workspace_bytes(1, lv.first, lv.second, sizeof(double)));
     }
     s.opwork = ar.raw(wbytes);
+    WB_HIP(hipEventCreateWithFlags(&s.main_ev, hipEventDisableTiming));
+    for (int k = 0; k < AUX_STREAMS; ++k) {
+      WB_HIP(hipStreamCreateWithFlags(&s.aux[k], hipStreamNonBlocking));
+      WB_HIP(hipEventCreateWithFlags(&s.aux_ev[k], hipEventDisableTiming));
+      s.aux_partial[k] = ar.alloc<double>(RED_BLOCKS + 64);
+      launch_fill<double>(st, s.aux_partial[k], 0.0, RED_BLOCKS + 64);  // the reduction counter
+      s.aux_work[k] = ar.raw(wbytes);
+    }
   }
+  SetupEstimates est;
   s.mu_q = ar.alloc<double>((size_t)m.E * n3);
   WB_HIP(hipMemcpyAsync(s.mu_q, mu_q, sizeof(double) * m.E * n3, hipMemcpyDeviceToDevice, st));
 
@@ -926,7 +1037,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   clk.mark("scratch + mu copy");
   s.pd.reset(new Precond<double>());
   Precond<double>& P = *s.pd;
-  build_hierarchy(s, P.A, 3, s.mu_q, 1000);
+  build_hierarchy(s, P.A, 3, s.mu_q, 1000, est);
   clk.mark("velocity hierarchy");
   // learned coarse correction: velocity level Q1 on N/2 (if it is a smoothed level)
   for (int li = 0; li + 1 < (int)P.A.L.size(); ++li)
@@ -950,9 +1061,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
              "learned correction needs a velocity level Q1 on N/2 above the coarsest");
   // weights C = M(a_l sqrt(mu)), D = M(a_r sqrt(mu)) (eq. 8, Sec. 5); stored inverted
   const double amps[2] = {o.a_l, o.a_r};
-  auto bh = make_bhat(m.k);
-  double* dbh = ar.alloc<double>(bh.size());
-  WB_HIP(hipMemcpy(dbh, bh.data(), sizeof(double) * bh.size(), hipMemcpyHostToDevice));
+  const double* dbh = const_table(make_bhat(m.k));
   alloc_work(s, P);
   for (int side = 0; side < 2; ++side) {
     P.winv[side] = ar.alloc<double>(m.nn);
@@ -964,7 +1073,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     // Poisson hierarchy on the coefficient 1/w at the Gauss points (eq. 11, 12)
     double* cq = ar.alloc<double>((size_t)m.E * n3);
     launch_poisson_coef(st, m.N, m.k, amps[side], s.mu_q, cq);
-    build_hierarchy(s, P.Pois[side], 1, cq, side == 0 ? 2000 : 3000);
+    build_hierarchy(s, P.Pois[side], 1, cq, side == 0 ? 2000 : 3000, est);
   }
   clk.mark("weights + Poisson hierarchies");
   // Chebyshev bounds on the discontinuous K_w levels
@@ -973,11 +1082,29 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     launch_splitmix_vec(st, pl, side == 0 ? 4000ULL : 5000ULL, 0, P.pr);
     launch_remove_mean<double>(st, m.E, m.np, P.pr, s.red_partial, s.red_out + 12);
     auto op = [&](const double* in, double* out) { apply_K<double>(s, P, side, in, out); };
-    const double lam = lanczos_max(s, op, pl, P.dk[side], o.lanczos_steps, P.pr, P.pd, P.pt, P.pm);
-    P.klmin[side] = 0.1 * lam;
-    P.klmax[side] = 1.1 * lam;
+    double* lz = next_lz(s, est, &P.klmin[side], &P.klmax[side]);
+    lanczos_enqueue(st, op, pl, P.dk[side], o.lanczos_steps, P.pr, P.pd, P.pt, P.pm, lz, s.red_partial);
   }
   clk.mark("K_w bounds");
+  // all eigenvalue estimates and the coarsest stencils: one host read
+  {
+    std::vector<double> h;
+    join_setup_estimates(s, est, h);
+    Hierarchy<double>* hs[3] = {&P.A, &P.Pois[0], &P.Pois[1]};
+    std::vector<std::vector<double>> Sh(3);
+    for (int i = 0; i < 3; ++i) {
+      const Level<double>& C = hs[i]->L.back();
+      Sh[i].resize(q1_stencil_len(C.NC, C.N));
+      WB_HIP(hipMemcpyAsync(Sh[i].data(), C.S, sizeof(double) * Sh[i].size(), hipMemcpyDeviceToHost, st));
+    }
+    WB_HIP(hipStreamSynchronize(st));
+    finish_setup_estimates(s, est, h);
+    std::vector<std::vector<double>> keep_d;
+    std::vector<std::vector<int>> keep_i;
+    for (int i = 0; i < 3; ++i) coarsest_inverse(s, *hs[i], Sh[i], keep_d, keep_i);
+    WB_HIP(hipStreamSynchronize(st));
+  }
+  clk.mark("estimates + coarsest inverses");
   if (o.precond_prec != WB_FP64) {
     s.pf.reset(new Precond<float>());
     Precond<float>& F = *s.pf;
