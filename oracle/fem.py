@@ -219,6 +219,19 @@ def element_div(k: int, h: float) -> np.ndarray:
     return Be
 
 
+def pressure_mass_diag(mesh: Mesh, mu_q: np.ndarray) -> np.ndarray:
+    """Diagonal of the inverse viscosity-weighted pressure mass M_p(1/mu) (Sec. 3.1, eq. 4):
+    [M_p(1/mu)]_{(e,m),(e,m)} = sum_q W_q |J| psi_m(x_q)^2 / mu_q, laid out [E][n_p].
+
+    Reading: the paper diagonalizes M_p(1/mu) by lumping against the coefficient vector of the
+    constant function.  In an L2-orthogonal (Legendre) modal basis that vector is the first
+    mode alone, and its lumped entries int psi_m / mu vanish for m > 0 wherever mu is constant,
+    so the diagonal of M_p(1/mu) is taken instead; for the constant mode the two coincide."""
+    R = reference(mesh.k)
+    detJ = (0.5 * mesh.h) ** 3
+    return np.einsum("q,qm,eq->em", R["W"] * detJ, R["Psi"] ** 2, 1.0 / mu_q).reshape(-1)
+
+
 def _vel_gdofs(mesh: Mesh) -> np.ndarray:
     return np.concatenate([c * mesh.n_nodes + mesh.elem_nodes for c in range(3)], axis=1)
 

@@ -5,6 +5,8 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 Written from the paper's definitions:
 
 * upper block-triangular right preconditioner and GMRES (eq. 3);
+* the inverse viscosity-weighted pressure mass Schur approximation, diagonalized (Sec. 3.1,
+  eq. 4; the comparison baseline of Sec. 8);
 * BFBT / w-BFBT inverse Schur approximation (eq. 7, 8) with lumped
   sqrt(mu)-weighted velocity masses and Dirichlet amplification (Sec. 5);
 * pressure Poisson K_w = B D_w^-1 B^T and its V-cycle through a continuous Q_k
@@ -296,8 +298,12 @@ class Stokes:
 class Preconditioner:
     """Upper block-triangular preconditioner (eq. 3) with multigrid blocks and w-BFBT."""
 
-    def __init__(self, st: Stokes, degree=3, schur_sign=-1):
+    def __init__(self, st: Stokes, degree=3, schur_sign=-1, schur="wbfbt"):
         self.st = st
+        # Schur approximation: w-BFBT (eq. 8) or the diagonal of M_p(1/mu) (eq. 4)
+        assert schur in ("wbfbt", "mass")
+        self.schur = schur
+        self.mass_diag = fem.pressure_mass_diag(st.mesh, st.mu_q)
         # Sign of the Schur block of the preconditioner.  The paper's S = B A^-1 B^T is the
         # negated Schur complement of the saddle matrix (footnote of Sec. 1.1), so the block
         # that approximates the saddle matrix's own Schur complement is -S~ (schur_sign = -1,
@@ -338,6 +344,10 @@ class Preconditioner:
         y = self.k_vcycle("r", st.remove_mean(r))
         return self.k_vcycle("l", st.remove_mean(st.middle(y)))
 
+    def mass_schur(self, r):
+        """Approximate S^-1 r by the inverse of the diagonalized M_p(1/mu), mean removed."""
+        return self.st.remove_mean(r / self.mass_diag)
+
     def a_vcycle(self, b):
         return self.A_mg.vcycle(b)
 
@@ -345,7 +355,8 @@ class Preconditioner:
         """[u~; p~] = P^-1 [r_u; r_p], P = [[A~, B^T], [0, schur_sign S~]] (eq. 3)."""
         st = self.st
         ru, rp = x[:st.nu], x[st.nu:]
-        zp = self.schur_sign * self.wbfbt(rp)
+        zs = self.wbfbt(rp) if self.schur == "wbfbt" else self.mass_schur(rp)
+        zp = self.schur_sign * zs
         zu = self.a_vcycle(ru - st.B.T @ zp)
         return np.concatenate([zu, zp])
 

@@ -230,3 +230,53 @@ def test_schur_sign_reading_matches_table3_iteration_count():
         assert hist[-1] <= 1e-6
     assert 20 <= its[-1] <= 60, its
     assert its[1] >= 1.5 * its[-1], its
+
+
+def test_pressure_mass_diagonal_closed_form_and_bruteforce():
+    """diag M_p(1/mu) (eq. 4): constant mu gives the Legendre norms (h/2)^3 prod 2/(2a+1) / mu;
+    for mu constant on each element the full element mass matrix (brute-force double loop over
+    modes and Gauss points) is diagonal with that diagonal."""
+    from oracle import fem
+    N, k = 3, 3
+    m = fem.Mesh(N, k)
+    R = fem.reference(k)
+    nq = R["n"] ** 3
+    rng = np.random.default_rng(3)
+    mu_e = 10.0 ** rng.uniform(-3, 3, m.E)
+    mu_q = np.repeat(mu_e[:, None], nq, axis=1)
+    d = fem.pressure_mass_diag(m, mu_q).reshape(m.E, m.n_p)
+    h3 = (0.5 * m.h) ** 3
+    norms = np.array([h3 * (2 / (2 * a + 1)) * (2 / (2 * b + 1)) * (2 / (2 * c + 1))
+                      for a, b, c in fem.modes(k)])
+    assert np.allclose(d, norms[None, :] / mu_e[:, None], rtol=1e-13, atol=0)
+    xq, wq = fem.gauss_rule(k + 1)
+    for e in (0, 7, m.E - 1):
+        Me = np.zeros((m.n_p, m.n_p))
+        for i, (a1, b1, c1) in enumerate(fem.modes(k)):
+            for j, (a2, b2, c2) in enumerate(fem.modes(k)):
+                s = 0.0
+                for qz in range(k + 1):
+                    for qy in range(k + 1):
+                        for qx in range(k + 1):
+                            L = lambda deg, t: np.polynomial.legendre.legval(t, [0] * deg + [1])
+                            p1 = L(a1, xq[qx]) * L(b1, xq[qy]) * L(c1, xq[qz])
+                            p2 = L(a2, xq[qx]) * L(b2, xq[qy]) * L(c2, xq[qz])
+                            s += wq[qx] * wq[qy] * wq[qz] * h3 * p1 * p2 / mu_e[e]
+                Me[i, j] = s
+        assert np.abs(Me - np.diag(np.diag(Me))).max() <= 1e-14 * np.abs(Me).max()
+        assert np.allclose(np.diag(Me), d[e], rtol=1e-13, atol=0)
+
+
+def test_mass_schur_baseline_needs_more_iterations_than_wbfbt():
+    """The comparison of Sec. 8 at a small size: with eight sinkers the diagonalized M_p(1/mu)
+    Schur approximation converges but needs well over the w-BFBT iteration count (oracle at
+    8^3 Q2: 88 against 39)."""
+    st = _small(N=8, k=2, n=8, dr=1e4, a_r=1.0, seed=11)
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    its = {}
+    for schur in ("wbfbt", "mass"):
+        P = solver.Preconditioner(st, schur=schur)
+        _, it, hist = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6, max_iter=300)
+        assert hist[-1] <= 1e-6, (schur, it)
+        its[schur] = it
+    assert its["mass"] >= 1.5 * its["wbfbt"], its
