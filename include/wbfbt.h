@@ -91,6 +91,11 @@ typedef struct {
                              takes at most this many MB (FP64) are applied as
                              stencils instead of element kernels (32); the coarsest
                              level is always assembled; 0: element kernels only   */
+  int schur_approx;       /* Schur block of the preconditioner: 0 (default) w-BFBT
+                             (eq. 8); 1 the inverse viscosity-weighted pressure
+                             mass M_p(1/mu) (eq. 4), diagonalized (its diagonal:
+                             entries sum_q W_q |J| psi_m^2 / mu_q), the comparison
+                             baseline of Sec. 8                                   */
 } wb_opts;
 
 typedef struct {
@@ -196,6 +201,7 @@ WB_API wb_status wb_subsolve(wb_solver* s, int which, const double* b, double* x
  *   4 inverse diagonal of K_l [E][n_p]  5 inverse diagonal of K_r [E][n_p]
  *   6 Poisson coefficient 1/w_l at `level`, 7 same for 1/w_r
  *   8 inverse Jacobi diagonal of the left Poisson operator at `level`
+ *   9 inverse of the diagonalized M_p(1/mu) (eq. 4) [E][n_p]
  * out_dev: DEVICE FP64 buffer of the stated size. */
 WB_API wb_status wb_solver_query(wb_solver* s, int what, int level, double* out_dev, void* stream);
 /* Hierarchy description: which = 0 velocity, 1 left Poisson, 2 right Poisson,

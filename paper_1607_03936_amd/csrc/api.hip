@@ -97,6 +97,7 @@ void wb_opts_default(wb_opts* o) {
   o->use_graph = 1;
   o->schur_sign = -1;
   o->assemble_mb = 32.0;
+  o->schur_approx = 0;
 }
 
 const char* wb_last_error(void) { return g_err.c_str(); }
@@ -427,6 +428,7 @@ wb_status wb_solver_query(wb_solver* sh, int what, int level, double* out, void*
       case 6: { auto& L = lev(P.Pois[0]); cp(L.coef, (size_t)L.E * (L.k + 1) * (L.k + 1) * (L.k + 1)); } break;
       case 7: { auto& L = lev(P.Pois[1]); cp(L.coef, (size_t)L.E * (L.k + 1) * (L.k + 1) * (L.k + 1)); } break;
       case 8: { auto& L = lev(P.Pois[0]); cp(L.dinv, L.len); } break;
+      case 9: cp(P.mpinv, (size_t)m.E * m.np); break;
       default: throw Error{WB_EINVAL, "unknown query"};
     }
     WB_HIP(hipStreamSynchronize(st));

@@ -96,6 +96,10 @@ struct TailArgs {
 template <typename T>
 void launch_vcycle_tail(hipStream_t st, const TailArgs<T>& a, const T* b, T* x);
 
+// Inverse of the diagonal of the inverse viscosity-weighted pressure mass M_p(1/mu) (eq. 4):
+// out[e n_p + m] = 1 / sum_q W_q |J| psi_m(x_q)^2 / mu_q (mu at the Gauss points).
+void launch_pmass_inv(hipStream_t st, int N, int k, const double* mu_q, double* out);
+
 // Jacobi diagonal (not inverted) of the NC-component operator, accumulated into diag (zeroed).
 void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* coef, double* diag);
 // dinv = 1/diag, 1 on Dirichlet nodes (if dir).

@@ -1448,6 +1448,27 @@ void stencil_dispatch(hipStream_t st, int N, const T* S, const T* u, T* y, bool 
   }
 }
 
+// Inverse of the diagonal of the inverse viscosity-weighted pressure mass M_p(1/mu) (eq. 4):
+// out[e n_p + m] = 1 / sum_q W_q |J| psi_m(x_q)^2 / mu_q, one thread per (element, mode).
+template <int n>
+__global__ void k_pmass_inv(const int E, const double hh, const double* __restrict__ mu_q,
+                            double* __restrict__ out) {
+  constexpr int NP = (n - 1) * n * (n + 1) / 6, N3 = n * n * n;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)E * NP) return;
+  const int e = (int)(idx / NP), r = (int)(idx % NP);
+  const int ma = CT<n>::t.ma[r], mb = CT<n>::t.mb[r], mc = CT<n>::t.mc[r];
+  const double* mu = mu_q + (size_t)e * N3;
+  double s = 0.0;
+  for (int qz = 0; qz < n; ++qz)
+    for (int qy = 0; qy < n; ++qy)
+      for (int qx = 0; qx < n; ++qx) {
+        const double psi = CT<n>::t.L[ma * n + qx] * CT<n>::t.L[mb * n + qy] * CT<n>::t.L[mc * n + qz];
+        s += CT<n>::t.wg[qx] * CT<n>::t.wg[qy] * CT<n>::t.wg[qz] * psi * psi / mu[qx + n * (qy + n * qz)];
+      }
+  out[idx] = 1.0 / (hh * hh * hh * s);
+}
+
 // ------------------------------------------------------------------ diagonals
 template <int n, int NC>
 __global__ void k_diag(const KT<n, double> tb, int N, int k, int M, int E, int nn, double hh, int dir,
@@ -2147,6 +2168,16 @@ template void launch_vcycle_tail<float>(hipStream_t, const TailArgs<float>&, con
     case 5: { constexpr int n = 5; __VA_ARGS__; } break;          \
     default: throw Error{WB_EUNSUPPORTED, "order not built"};     \
   }
+
+void launch_pmass_inv(hipStream_t st, int N, int k, const double* mu_q, double* out) {
+  const int E = N * N * N, np = tables(k).np;
+  const double hh = 0.5 / N;
+  WB_BY_ORDER(k, {
+    hipLaunchKernelGGL((k_pmass_inv<n>), dim3(grid_for((size_t)E * np, 256)), dim3(256), 0, st, E,
+                       hh, mu_q, out);
+  });
+  WB_HIP(hipGetLastError());
+}
 
 void launch_diag(hipStream_t st, int NC, int N, int k, bool dir, const double* coef, double* diag) {
   const int M = k * N + 1, E = N * N * N, nn = M * M * M, n3 = (k + 1) * (k + 1) * (k + 1);

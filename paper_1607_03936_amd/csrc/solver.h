@@ -73,6 +73,7 @@ struct Precond {
   Hierarchy<T> Pois[2];     // left / right Poisson hierarchies (coefficient 1/w)
   T* winv[2] = {nullptr, nullptr};  // C^-1, D^-1 per node [nn]
   T* dk[2] = {nullptr, nullptr};    // inverse diagonal of K_l, K_r [E*np]
+  T* mpinv = nullptr;               // inverse diagonal of M_p(1/mu) [E*np] (eq. 4)
   double klmin[2] = {0, 0}, klmax[2] = {0, 0};
   // work
   T *v1 = nullptr, *v2 = nullptr, *vt = nullptr;                       // velocity [3 nn]

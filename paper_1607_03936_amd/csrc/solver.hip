@@ -926,8 +926,14 @@ void apply_precond(Solver& s, Precond<T>& P, const T* ru, const T* rp, T* zu, T*
   hipStream_t st = s.st;
   const Mesh& m = s.m;
   const size_t vl = (size_t)3 * m.nn;
-  // P = [[A~, B^T], [0, sign S~]] (eq. 3): zp = sign S~^-1 rp, zu = A~^-1 (ru - B^T zp)
-  apply_wbfbt<T>(s, P, rp, zp);
+  // P = [[A~, B^T], [0, sign S~]] (eq. 3): zp = sign S~^-1 rp, zu = A~^-1 (ru - B^T zp), with
+  // S~ the w-BFBT approximation (eq. 8) or the diagonalized M_p(1/mu) (eq. 4)
+  if (s.o.schur_approx == 1) {
+    launch_mul<T>(st, (size_t)m.E * m.np, P.mpinv, rp, zp);
+    launch_remove_mean<T>(st, m.E, m.np, zp, s.red_partial, s.red_out + 2);
+  } else {
+    apply_wbfbt<T>(s, P, rp, zp);
+  }
   if (s.o.schur_sign < 0) launch_scal<T>(st, (size_t)m.E * m.np, T(-1), zp, zp);
   launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.v1, nullptr, zp, nullptr, nullptr, false,
                s.opwork);
@@ -999,6 +1005,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   WB_REQUIRE(o.p_schedule == 0 || o.p_schedule == 1, WB_EINVAL, "p_schedule must be 0 or 1");
   WB_REQUIRE(o.schur_sign == 1 || o.schur_sign == -1, WB_EINVAL, "schur_sign must be 1 or -1");
   WB_REQUIRE(o.assemble_mb >= 0.0, WB_EINVAL, "assemble_mb must be >= 0");
+  WB_REQUIRE(o.schur_approx == 0 || o.schur_approx == 1, WB_EINVAL, "schur_approx must be 0 or 1");
   WB_REQUIRE(o.precond_prec >= WB_FP64 && o.precond_prec <= WB_BF16X1, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
@@ -1063,6 +1070,8 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   const double amps[2] = {o.a_l, o.a_r};
   const double* dbh = const_table(make_bhat(m.k));
   alloc_work(s, P);
+  P.mpinv = ar.alloc<double>((size_t)m.E * m.np);
+  launch_pmass_inv(st, m.N, m.k, s.mu_q, P.mpinv);
   for (int side = 0; side < 2; ++side) {
     P.winv[side] = ar.alloc<double>(m.nn);
     launch_fill<double>(st, P.winv[side], 0.0, m.nn);
@@ -1118,6 +1127,8 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
       F.klmin[side] = P.klmin[side];
       F.klmax[side] = P.klmax[side];
     }
+    F.mpinv = ar.alloc<float>((size_t)m.E * m.np);
+    launch_cast<double, float>(st, (size_t)m.E * m.np, P.mpinv, F.mpinv);
     alloc_work(s, F);
   }
   clk.mark("FP32 copies");

@@ -32,7 +32,8 @@ class wb_opts(ctypes.Structure):
                 ("use_learned", ctypes.c_int), ("p_schedule", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("schur_sign", ctypes.c_int),
-                ("assemble_mb", ctypes.c_double)]
+                ("assemble_mb", ctypes.c_double),
+                ("schur_approx", ctypes.c_int)]
 
 
 class wb_report(ctypes.Structure):

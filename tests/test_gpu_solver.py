@@ -293,3 +293,34 @@ def test_assembled_q1_levels_match_element_kernels(name):
         assert rep.rel_res <= 1e-6
         its.append(rep.iters)
     assert abs(its[0] - its[1]) <= 1, its
+
+
+@pytest.mark.parametrize("name", ["n8k2", "n4k3"])
+def test_mass_schur_baseline_matches_oracle(name):
+    """The diagonalized M_p(1/mu) Schur approximation (eq. 4, the baseline of Sec. 8): its
+    inverse diagonal, the block preconditioner with it, and the FGMRES iteration count follow
+    the oracle."""
+    wb = _wb()
+    w, st, P, m, v, s = _pair(name)
+    om = st.mesh
+    sm = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, schur_approx=1)
+    Pm = solver.Preconditioner(st, schur="mass")
+    assert _rel(host(sm.query(9, 0, om.p_dof)), 1.0 / Pm.mass_diag) < 1e-13
+    ru = random_vector(61, om.u_dof)
+    ru[om.vel_boundary] = 0.0
+    rp = st.remove_mean(random_vector(62, om.p_dof))
+    zu = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    zp = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    sm.precond(dev(ru), dev(rp), zu, zp)
+    ref = Pm.apply(np.concatenate([ru[st.idx], rp]))
+    assert _rel(host(zp), ref[st.nu:]) < 1e-12
+    assert _rel(host(zu), st.embed_u(ref[:st.nu])) < 1e-9
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    u = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    p = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    rep = sm.solve(f, u, p)
+    assert rep.rel_res <= 1e-6
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    _, it_o, _ = solver.fgmres(st.stokes_matvec, b, Pm.apply, rtol=1e-6)
+    assert abs(rep.iters - it_o) <= 2, (rep.iters, it_o)
