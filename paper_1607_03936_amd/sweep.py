@@ -4,6 +4,7 @@ with the diagonalized inverse viscosity-weighted pressure mass M_p(1/mu) (eq. 4)
 (eq. 8), the same velocity multigrid for both.
 
 python -m paper_1607_03936_amd.sweep [--N 32] [--k 2] [--max-iter 1000] [--json out.json]
+                                    [--sinkers 1,4,...] [--ratios 1e4,...]
 
 Sinker sets: n in {1, 4, 8, 12, 16, 20, 24, 28}, centres from the seeded generator (seed 100 + n),
 delta 200, omega 0.1, beta 10, mu in [DR^-1/2, DR^1/2]; a_l = 1, a_r = max(1, (N/16) 2^(k-2)).
@@ -29,7 +30,11 @@ def main(argv=None):
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--sinkers", default=",".join(str(n) for n in SINKERS))
+    ap.add_argument("--ratios", default=",".join(f"{r:g}" for r in RATIOS))
     a = ap.parse_args(argv)
+    sinkers = [int(x) for x in a.sinkers.split(",")]
+    ratios = [float(x) for x in a.ratios.split(",")]
 
     import torch
 
@@ -42,9 +47,9 @@ def main(argv=None):
     u = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
     p = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
     rows = []
-    for n in SINKERS:
+    for n in sinkers:
         c = sinker_centers(100 + n, n)
-        for dr in RATIOS:
+        for dr in ratios:
             lo, hi = dr ** -0.5, dr ** 0.5
             v = wb.Viscosity.sinker(m, c, 200.0, 0.1, lo, hi)
             wb.wb_rhs_sinker(m, c, 200.0, 0.1, 10.0, f)
@@ -68,10 +73,10 @@ def main(argv=None):
         return f"{r['iters']}" if r["converged"] else f">{r['iters']}"
     for label, title in (("mass", "M_p(1/mu), diagonalized"), ("wbfbt", "w-BFBT")):
         print(f"\n{title}: FGMRES iterations, {a.N}^3 Q{a.k}, rows #sinkers, columns DR")
-        print(f"{'':>10}" + "".join(f"{dr:>10.0e}" for dr in RATIOS))
-        for n in SINKERS:
+        print(f"{'':>10}" + "".join(f"{dr:>10.0e}" for dr in ratios))
+        for n in sinkers:
             line = f"{'S%d-rand' % n:>10}"
-            for dr in RATIOS:
+            for dr in ratios:
                 r = next(x for x in rows if x["sinkers"] == n and x["dr"] == dr)
                 line += f"{cell(r[label]):>10}"
             print(line)
