@@ -4,7 +4,10 @@ with the diagonalized inverse viscosity-weighted pressure mass M_p(1/mu) (eq. 4)
 (eq. 8), the same velocity multigrid for both.
 
 python -m paper_1607_03936_amd.sweep [--N 32] [--k 2] [--max-iter 1000] [--json out.json]
-                                    [--sinkers 1,4,...] [--ratios 1e4,...]
+                                    [--sinkers 1,4,...] [--ratios 1e4,...] [--amp]
+
+--amp instead runs the boundary amplification study of Sec. 5 (Table 2): w-BFBT with
+a_l x a_r in {1, 2, 4, 8, 16, 32}^2 on S16 at DR 1e6 (or the given sinkers and ratio).
 
 Sinker sets: n in {1, 4, 8, 12, 16, 20, 24, 28}, centres from the seeded generator (seed 100 + n),
 delta 200, omega 0.1, beta 10, mu in [DR^-1/2, DR^1/2]; a_l = 1, a_r = max(1, (N/16) 2^(k-2)).
@@ -32,7 +35,10 @@ def main(argv=None):
     ap.add_argument("--json", default=None)
     ap.add_argument("--sinkers", default=",".join(str(n) for n in SINKERS))
     ap.add_argument("--ratios", default=",".join(f"{r:g}" for r in RATIOS))
+    ap.add_argument("--amp", action="store_true")
     a = ap.parse_args(argv)
+    if a.amp:
+        return amplification(a)
     sinkers = [int(x) for x in a.sinkers.split(",")]
     ratios = [float(x) for x in a.ratios.split(",")]
 
@@ -83,6 +89,43 @@ def main(argv=None):
     if a.json:
         with open(a.json, "w") as fh:
             json.dump({"N": a.N, "k": a.k, "max_iter": a.max_iter, "rows": rows}, fh, indent=1)
+
+
+AMPS = (1, 2, 4, 8, 16, 32)
+
+
+def amplification(a):
+    import torch
+
+    from paper_1607_03936_amd import wbfbt as wb
+    from synthetic import sinker_centers
+    wb.lib()
+    n = 16 if a.sinkers == ",".join(str(x) for x in SINKERS) else int(a.sinkers.split(",")[0])
+    dr = 1e6 if a.ratios == ",".join(f"{r:g}" for r in RATIOS) else float(a.ratios.split(",")[0])
+    m = wb.Mesh(a.N, a.k)
+    c = sinker_centers(100 + n, n)
+    v = wb.Viscosity.sinker(m, c, 200.0, 0.1, dr ** -0.5, dr ** 0.5)
+    f = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    u = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    p = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, c, 200.0, 0.1, 10.0, f)
+    its = {}
+    for al in AMPS:
+        for ar in AMPS:
+            s = wb.Solver(m, v, a_l=float(al), a_r=float(ar), max_iter=a.max_iter)
+            rep = s.solve(f, u, p, allow_noconv=True)
+            its[(al, ar)] = rep.iters if rep.rel_res <= 1e-6 else -rep.iters
+            del s
+        print(f"a_l {al}: " + " ".join(f"{abs(its[(al, ar)])}" for ar in AMPS), flush=True)
+    print(f"\nw-BFBT FGMRES iterations, {a.N}^3 Q{a.k}, S{n}-rand, DR {dr:.0e}; rows a_l, columns a_r")
+    print(f"{'':>6}" + "".join(f"{ar:>6}" for ar in AMPS))
+    for al in AMPS:
+        print(f"{al:>6}" + "".join(f"{(str(its[(al, ar)]) if its[(al, ar)] > 0 else '>' + str(-its[(al, ar)])):>6}"
+                                   for ar in AMPS))
+    if a.json:
+        with open(a.json, "w") as fh:
+            json.dump({"N": a.N, "k": a.k, "sinkers": n, "dr": dr,
+                       "iters": {f"{al},{ar}": v_ for (al, ar), v_ in its.items()}}, fh, indent=1)
 
 
 if __name__ == "__main__":
