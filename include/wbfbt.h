@@ -96,6 +96,10 @@ typedef struct {
                              mass M_p(1/mu) (eq. 4), diagonalized (its diagonal:
                              entries sum_q W_q |J| psi_m^2 / mu_q), the comparison
                              baseline of Sec. 8                                   */
+  int weights;            /* w-BFBT weight functions w_l = w_r (before the boundary
+                             amplification): 0 (default) sqrt(mu) (Sec. 4);
+                             1 (mu^2 + |grad mu|^2)^(1/4) (the remark of Sec. 4),
+                             grad mu of each element's Q_k interpolant of mu      */
 } wb_opts;
 
 typedef struct {

@@ -302,6 +302,39 @@ def lumped_weighted_mass(mesh: Mesh, w_nodes: np.ndarray, a_e: np.ndarray) -> np
     return d
 
 
+def interpolant_gradient(mesh: Mesh, f_nodes: np.ndarray, at: str = "nodes") -> np.ndarray:
+    """Gradient of the element-wise Q_k nodal interpolant of a nodal field, per element at its
+    GLL nodes (at="nodes") or at its Gauss points (at="gauss"): [E, n^3, 3]."""
+    n = mesh.n
+    xn = gll_points(n)
+    V, D = lagrange(xn, xn if at == "nodes" else gauss_rule(n)[0])
+    Gs = (kron3(V, V, D), kron3(V, D, V), kron3(D, V, V))      # d/dx, d/dy, d/dz
+    fe = f_nodes[mesh.elem_nodes]                               # [E, n^3]
+    return np.stack([fe @ G.T for G in Gs], axis=-1) * (2.0 / mesh.h)
+
+
+def gradient_weights(mesh: Mesh, mu_nodes: np.ndarray, mu_q: np.ndarray):
+    """Viscosity-gradient w-BFBT weights w = (mu^2 + |grad mu|^2)^(1/4) (remark in Sec. 4), with
+    grad mu the gradient of the element-wise Q_k interpolant of mu: per element at its nodes
+    [E, n^3] (for the lumped masses) and at the Gauss points [E, n^3] (for the Poisson
+    coefficient 1/w)."""
+    gn = interpolant_gradient(mesh, mu_nodes, "nodes")
+    gq = interpolant_gradient(mesh, mu_nodes, "gauss")
+    w_en = (mu_nodes[mesh.elem_nodes] ** 2 + (gn ** 2).sum(axis=-1)) ** 0.25
+    w_q = (mu_q ** 2 + (gq ** 2).sum(axis=-1)) ** 0.25
+    return w_en, w_q
+
+
+def lumped_weighted_mass_elem(mesh: Mesh, w_en: np.ndarray, a_e: np.ndarray) -> np.ndarray:
+    """lumped_weighted_mass with the weight given per element at its nodes [E, n^3] (a weight
+    that differs between the elements sharing a node)."""
+    wn = gll_weights(mesh.n)
+    Wq = kron3(wn, wn, wn) * mesh.h ** 3 / 8.0
+    d = np.zeros(mesh.n_nodes)
+    np.add.at(d, mesh.elem_nodes, a_e[:, None] * w_en * Wq[None, :])
+    return d
+
+
 def lumped_weighted_mass_gauss(mesh: Mesh, w_q: np.ndarray) -> np.ndarray:
     """Row sums of the weighted mass matrix with Gauss quadrature (comparison reading)."""
     R = reference(mesh.k)

@@ -212,7 +212,7 @@ class Stokes:
     """Assembled multi-sinker Stokes problem on the interior velocity DOFs."""
 
     def __init__(self, N, k, centers, delta, omega, mu_min, mu_max, beta=10.0,
-                 a_l=1.0, a_r=1.0, mu_fn=None, f_fn=None):
+                 a_l=1.0, a_r=1.0, mu_fn=None, f_fn=None, weights="sqrt"):
         self.mesh = m = fem.Mesh(N, k)
         xq = m.quad_points()
         if mu_fn is None:
@@ -230,9 +230,17 @@ class Stokes:
         self.B = self.Bfull[:, self.idx].tocsr()
         self.F = self.Ffull[self.idx]
         self.a_l, self.a_r = a_l, a_r
-        sq = np.sqrt(self.mu_nodes)
-        self.C_nodes = fem.lumped_weighted_mass(m, sq, fem.element_amplification(m, a_l))
-        self.D_nodes = fem.lumped_weighted_mass(m, sq, fem.element_amplification(m, a_r))
+        # w-BFBT weights: sqrt(mu) (Sec. 4) or the viscosity-gradient form of the remark there
+        if weights == "sqrt":
+            sq = np.sqrt(self.mu_nodes)
+            self.C_nodes = fem.lumped_weighted_mass(m, sq, fem.element_amplification(m, a_l))
+            self.D_nodes = fem.lumped_weighted_mass(m, sq, fem.element_amplification(m, a_r))
+            self.w_q = np.sqrt(self.mu_q)
+        else:
+            assert weights == "grad"
+            w_en, self.w_q = fem.gradient_weights(m, self.mu_nodes, self.mu_q)
+            self.C_nodes = fem.lumped_weighted_mass_elem(m, w_en, fem.element_amplification(m, a_l))
+            self.D_nodes = fem.lumped_weighted_mass_elem(m, w_en, fem.element_amplification(m, a_r))
         self.Cinv = 1.0 / np.tile(self.C_nodes, 3)[self.idx]
         self.Dinv = 1.0 / np.tile(self.D_nodes, 3)[self.idx]
         self.Kl = (self.B @ sp.diags(self.Cinv) @ self.B.T).tocsr()
@@ -313,9 +321,8 @@ class Preconditioner:
         m = st.mesh
         # velocity hierarchy on mu (Sec. 6), Poisson hierarchies on 1/w (eq. 11, 12, Sec. 5)
         self.A_mg = Hierarchy(m.N, m.k, st.mu_q, "velocity", 1000, degree)
-        sqmu = np.sqrt(st.mu_q)
-        c_l = 1.0 / (fem.element_amplification(m, st.a_l)[:, None] * sqmu)
-        c_r = 1.0 / (fem.element_amplification(m, st.a_r)[:, None] * sqmu)
+        c_l = 1.0 / (fem.element_amplification(m, st.a_l)[:, None] * st.w_q)
+        c_r = 1.0 / (fem.element_amplification(m, st.a_r)[:, None] * st.w_q)
         self.Pl_mg = Hierarchy(m.N, m.k, c_l, "poisson", 2000, degree)
         self.Pr_mg = Hierarchy(m.N, m.k, c_r, "poisson", 3000, degree)
         self.I = fem.modal_projection(m)

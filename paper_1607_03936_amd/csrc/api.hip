@@ -98,6 +98,7 @@ void wb_opts_default(wb_opts* o) {
   o->schur_sign = -1;
   o->assemble_mb = 32.0;
   o->schur_approx = 0;
+  o->weights = 0;
 }
 
 const char* wb_last_error(void) { return g_err.c_str(); }

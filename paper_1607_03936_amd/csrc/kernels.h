@@ -126,6 +126,13 @@ void launch_load(hipStream_t st, int N, int k, const double* f_q, double* F);
 // Coefficient transforms at the Gauss points: c = scale / (amp_e sqrt(mu)) with amp_e on
 // boundary elements (Poisson coefficient 1/w of eq. 11-12 and Sec. 5) or a plain FP64->FP32 cast.
 void launch_poisson_coef(hipStream_t st, int N, int k, double amp, const double* mu_q, double* c_q);
+// The same two products with the viscosity-gradient weights w = (mu^2 + |grad mu|^2)^(1/4) of the
+// remark in Sec. 4, grad mu from each element's Q_k interpolant of mu_nodes: the lumped mass per
+// element node (accumulated into cnodes, zeroed) and 1/(a_e w) at the Gauss points.
+void launch_lumped_mass_grad(hipStream_t st, int N, int k, double amp, const double* mu_nodes,
+                             double* cnodes);
+void launch_poisson_coef_grad(hipStream_t st, int N, int k, double amp, const double* mu_q,
+                              const double* mu_nodes, double* c_q);
 
 // Transfers: tensor product of a 1D sparse matrix (rows: cnt / col / val, width W).
 // lin21 marks the rows of linear interpolation between nested node lines with

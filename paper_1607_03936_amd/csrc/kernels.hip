@@ -1616,6 +1616,60 @@ __global__ void k_load(const KT<n, double> tb, int N, int k, int M, int E, doubl
   atomic_add(&F[2 * nn + gi + (long long)M * (gj + (long long)M * gl)], s * h3);
 }
 
+// Viscosity-gradient weights w = (mu^2 + |grad mu|^2)^(1/4), grad mu of the element's Q_k
+// interpolant of mu_nodes.  Lumped mass: per element node, accumulated as in k_lumped.
+template <int n>
+__global__ void k_lumped_grad(int N, int M, int E, double h3, double s, double amp,
+                              const double* __restrict__ mu_nodes, double* __restrict__ cn) {
+  constexpr int NN = n * n, N3 = NN * n, k = n - 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)E * N3) return;
+  const int e = (int)(idx / N3), li = (int)(idx % N3);
+  const int a = li % n, b = (li / n) % n, c = li / NN;
+  const int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
+  const bool touch = ex == 0 || ex == N - 1 || ey == 0 || ey == N - 1 || ez == 0 || ez == N - 1;
+  auto mu = [&](int i, int j, int l) {
+    return mu_nodes[(ex * k + i) + M * ((ey * k + j) + M * (ez * k + l))];
+  };
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int l = 0; l < n; ++l) {
+    gx += CT<n>::t.DN[a * n + l] * mu(l, b, c);
+    gy += CT<n>::t.DN[b * n + l] * mu(a, l, c);
+    gz += CT<n>::t.DN[c * n + l] * mu(a, b, l);
+  }
+  const double m0 = mu(a, b, c);
+  const double w = sqrt(sqrt(m0 * m0 + s * s * (gx * gx + gy * gy + gz * gz)));
+  const int g = (ex * k + a) + M * ((ey * k + b) + M * (ez * k + c));
+  atomic_add(&cn[g], (touch ? amp : 1.0) * w * CT<n>::t.wl[a] * CT<n>::t.wl[b] * CT<n>::t.wl[c] * h3);
+}
+
+// Poisson coefficient 1/(a_e w) at the Gauss points with the gradient weights.
+template <int n>
+__global__ void k_poisson_coef_grad(int N, int M, int E, double s, double amp,
+                                    const double* __restrict__ mu_q, const double* __restrict__ mu_nodes,
+                                    double* __restrict__ c) {
+  constexpr int NN = n * n, N3 = NN * n, k = n - 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)E * N3) return;
+  const int e = (int)(idx / N3), q = (int)(idx % N3);
+  const int qx = q % n, qy = (q / n) % n, qz = q / NN;
+  const int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
+  const bool touch = ex == 0 || ex == N - 1 || ey == 0 || ey == N - 1 || ez == 0 || ez == N - 1;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int l3 = 0; l3 < n; ++l3)
+    for (int l2 = 0; l2 < n; ++l2)
+      for (int l1 = 0; l1 < n; ++l1) {
+        const double v = mu_nodes[(ex * k + l1) + M * ((ey * k + l2) + M * (ez * k + l3))];
+        const double bx = CT<n>::t.B[qx * n + l1], by = CT<n>::t.B[qy * n + l2], bz = CT<n>::t.B[qz * n + l3];
+        gx += CT<n>::t.D1[qx * n + l1] * by * bz * v;
+        gy += bx * CT<n>::t.D1[qy * n + l2] * bz * v;
+        gz += bx * by * CT<n>::t.D1[qz * n + l3] * v;
+      }
+  const double m0 = mu_q[idx];
+  const double w = sqrt(sqrt(m0 * m0 + s * s * (gx * gx + gy * gy + gz * gz)));
+  c[idx] = 1.0 / ((touch ? amp : 1.0) * w);
+}
+
 __global__ void k_poisson_coef(int N, int n3, int E, double amp, const double* __restrict__ mu_q,
                                double* __restrict__ c) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2168,6 +2222,26 @@ template void launch_vcycle_tail<float>(hipStream_t, const TailArgs<float>&, con
     case 5: { constexpr int n = 5; __VA_ARGS__; } break;          \
     default: throw Error{WB_EUNSUPPORTED, "order not built"};     \
   }
+
+void launch_lumped_mass_grad(hipStream_t st, int N, int k, double amp, const double* mu_nodes,
+                             double* cnodes) {
+  const int M = k * N + 1, E = N * N * N, n3 = (k + 1) * (k + 1) * (k + 1);
+  const double h = 1.0 / N, h3 = 0.125 * h * h * h, s = 2.0 / h;
+  WB_BY_ORDER(k, {
+    hipLaunchKernelGGL((k_lumped_grad<n>), dim3(grid_for((size_t)E * n3, 256)), dim3(256), 0, st, N,
+                       M, E, h3, s, amp, mu_nodes, cnodes);
+  });
+}
+
+void launch_poisson_coef_grad(hipStream_t st, int N, int k, double amp, const double* mu_q,
+                              const double* mu_nodes, double* c_q) {
+  const int M = k * N + 1, E = N * N * N, n3 = (k + 1) * (k + 1) * (k + 1);
+  const double s = 2.0 * N;
+  WB_BY_ORDER(k, {
+    hipLaunchKernelGGL((k_poisson_coef_grad<n>), dim3(grid_for((size_t)E * n3, 256)), dim3(256), 0,
+                       st, N, M, E, s, amp, mu_q, mu_nodes, c_q);
+  });
+}
 
 void launch_pmass_inv(hipStream_t st, int N, int k, const double* mu_q, double* out) {
   const int E = N * N * N, np = tables(k).np;

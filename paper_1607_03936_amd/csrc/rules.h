@@ -16,6 +16,7 @@ struct Tables {
   double xl[NMAX], wl[NMAX];           // GLL nodes / weights
   double B[NMAX * NMAX];               // B[q*n+a] = l_a(xg_q), GLL Lagrange at Gauss points
   double D1[NMAX * NMAX];              // D1[q*n+a] = l_a'(xg_q)
+  double DN[NMAX * NMAX];              // DN[p*n+a] = l_a'(xl_p), GLL Lagrange at GLL nodes
   double Dh[NMAX * NMAX];              // Dh[q*n+p] = derivative at xg_q of Gauss-Lagrange l^G_p
   double L[NMAX * NMAX];               // L[a*n+q] = P_a(xg_q)
   double J[NMAX * NMAX];               // J[a*n+i] = sum_q wg_q P_a(xg_q) B[q,i] / (2/(2a+1))
@@ -157,6 +158,8 @@ constexpr Tables build_tables(int k) {
   gauss_rule(n, t.xg, t.wg);
   gll_rule(n, t.xl, t.wl);
   lagrange(n, t.xl, n, t.xg, t.B, t.D1);
+  double Vl[NMAX * NMAX] = {};
+  lagrange(n, t.xl, n, t.xl, Vl, t.DN);
   double Vg[NMAX * NMAX] = {};
   lagrange(n, t.xg, n, t.xg, Vg, t.Dh);
   for (int a = 0; a < n; ++a)

@@ -1006,6 +1006,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   WB_REQUIRE(o.schur_sign == 1 || o.schur_sign == -1, WB_EINVAL, "schur_sign must be 1 or -1");
   WB_REQUIRE(o.assemble_mb >= 0.0, WB_EINVAL, "assemble_mb must be >= 0");
   WB_REQUIRE(o.schur_approx == 0 || o.schur_approx == 1, WB_EINVAL, "schur_approx must be 0 or 1");
+  WB_REQUIRE(o.weights == 0 || o.weights == 1, WB_EINVAL, "weights must be 0 or 1");
   WB_REQUIRE(o.precond_prec >= WB_FP64 && o.precond_prec <= WB_BF16X1, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
@@ -1075,13 +1076,15 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   for (int side = 0; side < 2; ++side) {
     P.winv[side] = ar.alloc<double>(m.nn);
     launch_fill<double>(st, P.winv[side], 0.0, m.nn);
-    launch_lumped_mass(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
+    if (o.weights == 1) launch_lumped_mass_grad(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
+    else launch_lumped_mass(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
     launch_invert_diag(st, 1, m.N, m.k, false, P.winv[side]);
     P.dk[side] = ar.alloc<double>((size_t)m.E * m.np);
     launch_diag_K(st, m.N, m.k, dbh, P.winv[side], P.dk[side]);
     // Poisson hierarchy on the coefficient 1/w at the Gauss points (eq. 11, 12)
     double* cq = ar.alloc<double>((size_t)m.E * n3);
-    launch_poisson_coef(st, m.N, m.k, amps[side], s.mu_q, cq);
+    if (o.weights == 1) launch_poisson_coef_grad(st, m.N, m.k, amps[side], s.mu_q, mu_nodes, cq);
+    else launch_poisson_coef(st, m.N, m.k, amps[side], s.mu_q, cq);
     build_hierarchy(s, P.Pois[side], 1, cq, side == 0 ? 2000 : 3000, est);
   }
   clk.mark("weights + Poisson hierarchies");

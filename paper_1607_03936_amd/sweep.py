@@ -8,6 +8,8 @@ python -m paper_1607_03936_amd.sweep [--N 32] [--k 2] [--max-iter 1000] [--json 
 
 --amp instead runs the boundary amplification study of Sec. 5 (Table 2): w-BFBT with
 a_l x a_r in {1, 2, 4, 8, 16, 32}^2 on S16 at DR 1e6 (or the given sinkers and ratio).
+--weights instead compares the w-BFBT weights sqrt(mu) and (mu^2 + |grad mu|^2)^(1/4) (the
+remark of Sec. 4) over the given sinkers and ratios.
 
 Sinker sets: n in {1, 4, 8, 12, 16, 20, 24, 28}, centres from the seeded generator (seed 100 + n),
 delta 200, omega 0.1, beta 10, mu in [DR^-1/2, DR^1/2]; a_l = 1, a_r = max(1, (N/16) 2^(k-2)).
@@ -36,11 +38,14 @@ def main(argv=None):
     ap.add_argument("--sinkers", default=",".join(str(n) for n in SINKERS))
     ap.add_argument("--ratios", default=",".join(f"{r:g}" for r in RATIOS))
     ap.add_argument("--amp", action="store_true")
+    ap.add_argument("--weights", action="store_true")
     a = ap.parse_args(argv)
-    if a.amp:
-        return amplification(a)
     sinkers = [int(x) for x in a.sinkers.split(",")]
     ratios = [float(x) for x in a.ratios.split(",")]
+    if a.amp:
+        return amplification(a)
+    if a.weights:
+        return weight_forms(a, sinkers, ratios)
 
     import torch
 
@@ -92,6 +97,37 @@ def main(argv=None):
 
 
 AMPS = (1, 2, 4, 8, 16, 32)
+
+
+def weight_forms(a, sinkers, ratios):
+    import torch
+
+    from paper_1607_03936_amd import wbfbt as wb
+    from synthetic import sinker_centers
+    wb.lib()
+    m = wb.Mesh(a.N, a.k)
+    a_r = max(1.0, (a.N / 16) * 2.0 ** (a.k - 2))
+    f = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    u = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    p = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    rows = []
+    for n in sinkers:
+        c = sinker_centers(100 + n, n)
+        for dr in ratios:
+            v = wb.Viscosity.sinker(m, c, 200.0, 0.1, dr ** -0.5, dr ** 0.5)
+            wb.wb_rhs_sinker(m, c, 200.0, 0.1, 10.0, f)
+            rec = {"sinkers": n, "dr": dr}
+            for label, wf in (("sqrt", 0), ("grad", 1)):
+                s = wb.Solver(m, v, a_l=1.0, a_r=a_r, weights=wf, max_iter=a.max_iter)
+                rep = s.solve(f, u, p, allow_noconv=True)
+                rec[label] = rep.iters if rep.rel_res <= 1e-6 else -rep.iters
+                del s
+            rows.append(rec)
+            print(f"S{n}-rand DR {dr:.0e}: sqrt(mu) {abs(rec['sqrt'])}  gradient {abs(rec['grad'])}",
+                  flush=True)
+    if a.json:
+        with open(a.json, "w") as fh:
+            json.dump({"N": a.N, "k": a.k, "rows": rows}, fh, indent=1)
 
 
 def amplification(a):

@@ -33,7 +33,8 @@ class wb_opts(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("schur_sign", ctypes.c_int),
                 ("assemble_mb", ctypes.c_double),
-                ("schur_approx", ctypes.c_int)]
+                ("schur_approx", ctypes.c_int),
+                ("weights", ctypes.c_int)]
 
 
 class wb_report(ctypes.Structure):

@@ -258,3 +258,26 @@ def test_coefficient_h_coarsening_reproduces_linear_fields():
     wf = fem.kron3(*[fem.gauss_rule(n)[1]] * 3)
     coarse = fem.coarsen_coefficient_h(fine, Nf, n)
     assert abs((fine @ wf).sum() / 8 - (coarse @ wf).sum()) < 1e-12
+
+
+def test_interpolant_gradient_and_gradient_weights():
+    """The gradient of the element-wise Q_k interpolant is exact for polynomials of degree k
+    (at the nodes and at the Gauss points); for a constant viscosity the gradient weights are
+    sqrt(mu), so the lumped masses and the Poisson coefficient equal the sqrt(mu) ones."""
+    for N, k in ((3, 2), (2, 3)):
+        m = fem.Mesh(N, k)
+        x = m.node_xyz
+        f = lambda X: 1.0 + 2 * X[..., 0] ** k - 3 * X[..., 1] * X[..., 2] ** (k - 1) + X[..., 2]
+        df = lambda X: np.stack([2 * k * X[..., 0] ** (k - 1), -3 * X[..., 2] ** (k - 1),
+                                 -3 * (k - 1) * X[..., 1] * X[..., 2] ** (k - 2) + 1.0], axis=-1)
+        gn = fem.interpolant_gradient(m, f(x), "nodes")
+        assert np.allclose(gn, df(x[m.elem_nodes]), rtol=0, atol=1e-11)
+        xq = m.quad_points()
+        gq = fem.interpolant_gradient(m, f(x), "gauss")
+        assert np.allclose(gq, df(xq), rtol=0, atol=1e-11)
+        mu = 7.0
+        w_en, w_q = fem.gradient_weights(m, np.full(m.n_nodes, mu), np.full((m.E, m.n ** 3), mu))
+        assert np.allclose(w_q, np.sqrt(mu), rtol=1e-15)
+        a_e = fem.element_amplification(m, 3.0)
+        assert np.allclose(fem.lumped_weighted_mass_elem(m, w_en, a_e),
+                           fem.lumped_weighted_mass(m, np.full(m.n_nodes, np.sqrt(mu)), a_e), rtol=1e-13)
