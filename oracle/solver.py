@@ -230,19 +230,36 @@ class Stokes:
         self.B = self.Bfull[:, self.idx].tocsr()
         self.F = self.Ffull[self.idx]
         self.a_l, self.a_r = a_l, a_r
-        # w-BFBT weights: sqrt(mu) (Sec. 4) or the viscosity-gradient form of the remark there
+        # BFBT weighting matrices: w-BFBT with sqrt(mu) (Sec. 4) or the viscosity-gradient weights
+        # of the remark there, or diag(A)-BFBT (C = D = diag(A), Sec. 4)
+        self.weights = weights
         if weights == "sqrt":
             sq = np.sqrt(self.mu_nodes)
             self.C_nodes = fem.lumped_weighted_mass(m, sq, fem.element_amplification(m, a_l))
             self.D_nodes = fem.lumped_weighted_mass(m, sq, fem.element_amplification(m, a_r))
             self.w_q = np.sqrt(self.mu_q)
-        else:
-            assert weights == "grad"
+        elif weights == "grad":
             w_en, self.w_q = fem.gradient_weights(m, self.mu_nodes, self.mu_q)
             self.C_nodes = fem.lumped_weighted_mass_elem(m, w_en, fem.element_amplification(m, a_l))
             self.D_nodes = fem.lumped_weighted_mass_elem(m, w_en, fem.element_amplification(m, a_r))
-        self.Cinv = 1.0 / np.tile(self.C_nodes, 3)[self.idx]
-        self.Dinv = 1.0 / np.tile(self.D_nodes, 3)[self.idx]
+        else:
+            assert weights == "diagA"
+            # Reading: the K_w multigrid needs a Poisson coefficient 1/w; diag(A) is taken as the
+            # lumped mass of an effective weight, w_eff(x_i) = mean_c diag(A)_(i,c) / m_i (m the
+            # unweighted lumped mass), and the coefficient is the element mean of the nodal 1/w_eff
+            # (a Q_k interpolant of the nodal values can turn negative between nodes of strongly
+            # different weight)
+            dA = self.Afull.diagonal().reshape(3, m.n_nodes)
+            mass = fem.lumped_weighted_mass(m, np.ones(m.n_nodes), np.ones(m.E))
+            self.w_eff = dA.mean(axis=0) / mass
+            c_e = (1.0 / self.w_eff[m.elem_nodes]).mean(axis=1)
+            self.w_q = np.repeat((1.0 / c_e)[:, None], m.n ** 3, axis=1)
+            self.C_nodes = self.D_nodes = None
+        if weights == "diagA":
+            self.Cinv = self.Dinv = 1.0 / self.A.diagonal()
+        else:
+            self.Cinv = 1.0 / np.tile(self.C_nodes, 3)[self.idx]
+            self.Dinv = 1.0 / np.tile(self.D_nodes, 3)[self.idx]
         self.Kl = (self.B @ sp.diags(self.Cinv) @ self.B.T).tocsr()
         self.Kr = (self.B @ sp.diags(self.Dinv) @ self.B.T).tocsr()
         self.nu, self.np_ = len(self.idx), m.p_dof
