@@ -96,10 +96,13 @@ typedef struct {
                              mass M_p(1/mu) (eq. 4), diagonalized (its diagonal:
                              entries sum_q W_q |J| psi_m^2 / mu_q), the comparison
                              baseline of Sec. 8                                   */
-  int weights;            /* w-BFBT weight functions w_l = w_r (before the boundary
-                             amplification): 0 (default) sqrt(mu) (Sec. 4);
+  int weights;            /* BFBT weighting: w-BFBT with w_l = w_r (before the boundary
+                             amplification) 0 (default) sqrt(mu) (Sec. 4) or
                              1 (mu^2 + |grad mu|^2)^(1/4) (the remark of Sec. 4),
-                             grad mu of each element's Q_k interpolant of mu      */
+                             grad mu of each element's Q_k interpolant of mu;
+                             2 diag(A)-BFBT: C = D = diag(A) per velocity DOF,
+                             K_w Poisson coefficient the element mean of the nodal
+                             lumped mass / diag(A) (no amplification unless set) */
 } wb_opts;
 
 typedef struct {
@@ -200,6 +203,7 @@ WB_API wb_status wb_subsolve(wb_solver* s, int which, const double* b, double* x
 
 /* Inspection of setup products (for tests).  what:
  *   0 C^-1 per node [n_nodes]          1 D^-1 per node [n_nodes]
+ *     (weights = 2: per velocity DOF [3][n_nodes])
  *   2 inverse Jacobi diagonal of A at `level` [3][n_nodes(level)]
  *   3 coarsened viscosity at `level` [E(level)][(k(level)+1)^3]
  *   4 inverse diagonal of K_l [E][n_p]  5 inverse diagonal of K_r [E][n_p]

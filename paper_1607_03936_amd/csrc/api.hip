@@ -420,8 +420,8 @@ wb_status wb_solver_query(wb_solver* sh, int what, int level, double* out, void*
       return H.L[level];
     };
     switch (what) {
-      case 0: cp(P.winv[0], m.nn); break;
-      case 1: cp(P.winv[1], m.nn); break;
+      case 0: cp(P.winv[0], (s.o.weights == 2 ? 3 : 1) * (size_t)m.nn); break;
+      case 1: cp(P.winv[1], (s.o.weights == 2 ? 3 : 1) * (size_t)m.nn); break;
       case 2: { auto& L = lev(P.A); cp(L.dinv, L.len); } break;
       case 3: { auto& L = lev(P.A); cp(L.coef, (size_t)L.E * (L.k + 1) * (L.k + 1) * (L.k + 1)); } break;
       case 4: cp(P.dk[0], (size_t)m.E * m.np); break;

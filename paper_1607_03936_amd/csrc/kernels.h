@@ -110,8 +110,14 @@ void launch_invert_diag(hipStream_t st, int NC, int N, int k, bool dir, double* 
 void launch_lumped_mass(hipStream_t st, int N, int k, double amp, const double* mu_nodes,
                         double* cnodes);
 // dinvK[e*np+m] = 1 / sum_{c,i interior} (B_e[m,(c,i)])^2 dinv_nodes[g(e,i)]
+// (per_component: dinv_nodes is [3][n_nodes], one weight per velocity DOF, as for diag(A)-BFBT)
 void launch_diag_K(hipStream_t st, int N, int k, const double* bhat, const double* dinv_nodes,
-                   double* dinvK);
+                   double* dinvK, bool per_component = false);
+// diag(A)-BFBT Poisson coefficient at the Gauss points, constant per element: the element mean
+// of m_i / mean_c diag3[c][i] over its nodes (diag3 the unmasked diag(A), mass the unweighted
+// lumped velocity mass), divided by the boundary amplification a_e.
+void launch_diag_a_coef(hipStream_t st, int N, int k, double amp, const double* diag3,
+                        const double* mass, double* c_q);
 
 // Multi-sinker viscosity at Gauss points (mu_q) and/or body-force z-component (f_q),
 // and at the velocity nodes.

@@ -1532,7 +1532,8 @@ __global__ void k_lumped(const KT<n, double> tb, int N, int k, int M, int E, dou
 
 template <int n>
 __global__ void k_diag_K(int N, int k, int M, int E, int np, double s2, const double* __restrict__ bhat,
-                         const double* __restrict__ dinv_nodes, double* __restrict__ dk) {
+                         const double* __restrict__ dinv_nodes, const int cstride,
+                         double* __restrict__ dk) {
   constexpr int NN = n * n, N3 = NN * n;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)E * np) return;
@@ -1544,10 +1545,9 @@ __global__ void k_diag_K(int N, int k, int M, int E, int np, double s2, const do
     const int gi = ex * k + a, gj = ey * k + b, gl = ez * k + c;
     if (gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1 || gl == 0 || gl == M - 1) continue;
     const int g = gi + M * (gj + M * gl);
-    const double di = dinv_nodes[g];
     for (int cc = 0; cc < 3; ++cc) {
       const double v = s2 * bhat[((size_t)m * 3 + cc) * N3 + li];
-      s += v * v * di;
+      s += v * v * dinv_nodes[(size_t)cc * cstride + g];
     }
   }
   dk[idx] = 1.0 / s;
@@ -2285,12 +2285,44 @@ void launch_lumped_mass(hipStream_t st, int N, int k, double amp, const double* 
 }
 
 void launch_diag_K(hipStream_t st, int N, int k, const double* bhat, const double* dinv_nodes,
-                   double* dk) {
+                   double* dk, bool per_component) {
   const int M = k * N + 1, E = N * N * N, np = tables(k).np;
   const double hh = 0.5 / N;
+  const int cstride = per_component ? M * M * M : 0;
   WB_BY_ORDER(k, {
     hipLaunchKernelGGL((k_diag_K<n>), dim3(grid_for((size_t)E * np, 256)), dim3(256), 0, st, N, k,
-                       M, E, np, hh * hh, bhat, dinv_nodes, dk);
+                       M, E, np, hh * hh, bhat, dinv_nodes, cstride, dk);
+  });
+}
+
+// diag(A)-BFBT Poisson coefficient: per element the mean over its nodes of m_i / w_i with
+// w_i = (diag_0 + diag_1 + diag_2)(i) / 3 the component mean of the unmasked diag(A) and m_i the
+// unweighted lumped mass (so 1/w_eff, w_eff = diag(A) / m), divided by a_e; constant on the element.
+template <int n>
+__global__ void k_diag_a_coef(int N, int M, int E, double amp, const double* __restrict__ diag3,
+                              const double* __restrict__ mass, double* __restrict__ c) {
+  constexpr int N3 = n * n * n, k = n - 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
+  const bool touch = ex == 0 || ex == N - 1 || ey == 0 || ey == N - 1 || ez == 0 || ez == N - 1;
+  const size_t nn = (size_t)M * M * M;
+  double s = 0.0;
+  for (int li = 0; li < N3; ++li) {
+    const int a = li % n, b = (li / n) % n, cc = li / (n * n);
+    const size_t g = (size_t)(ex * k + a) + M * ((size_t)(ey * k + b) + M * (size_t)(ez * k + cc));
+    s += 3.0 * mass[g] / (diag3[g] + diag3[nn + g] + diag3[2 * nn + g]);
+  }
+  const double ce = s / N3 / (touch ? amp : 1.0);
+  for (int q = 0; q < N3; ++q) c[(size_t)e * N3 + q] = ce;
+}
+
+void launch_diag_a_coef(hipStream_t st, int N, int k, double amp, const double* diag3,
+                        const double* mass, double* c_q) {
+  const int M = k * N + 1, E = N * N * N;
+  WB_BY_ORDER(k, {
+    hipLaunchKernelGGL((k_diag_a_coef<n>), dim3(grid_for((size_t)E, 256)), dim3(256), 0, st, N, M, E,
+                       amp, diag3, mass, c_q);
   });
 }
 

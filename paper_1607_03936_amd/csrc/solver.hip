@@ -811,14 +811,24 @@ const T* fine_mu(Solver& s, Precond<T>& P) {
   return P.A.L[0].coef;
 }
 
+// The weight inverse of `side` as the operators' per-node input scaling; with one weight per
+// velocity DOF (diag(A)-BFBT) the vector v is scaled here instead and no node scaling is used.
+template <typename T>
+const T* weight_scaling(Solver& s, Precond<T>& P, int side, T* v) {
+  if (s.o.weights != 2) return P.winv[side];
+  launch_mul<T>(s.st, (size_t)3 * s.m.nn, P.winv[side], v, v);
+  return nullptr;
+}
+
 template <typename T>
 void apply_K(Solver& s, Precond<T>& P, int side, const T* p, T* y) {
   hipStream_t st = s.st;
   const Mesh& m = s.m;
   launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr,
                nullptr, false, s.opwork);
-  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y,
-               P.winv[side], false, nullptr);
+  const T* sc = weight_scaling<T>(s, P, side, P.vt);
+  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr, y, sc,
+               false, nullptr);
 }
 
 // K_w p with an epilogue on the divergence kernel's output (see Epi).
@@ -828,8 +838,9 @@ void apply_K_epi(Solver& s, Precond<T>& P, int side, const T* p, const Epi<T>& e
   const Mesh& m = s.m;
   launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.vt, nullptr, p, nullptr,
                nullptr, false, s.opwork);
+  const T* sc = weight_scaling<T>(s, P, side, P.vt);
   launch_op_epi<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.vt, nullptr, nullptr, nullptr,
-                   nullptr, P.winv[side], false, nullptr, e);
+                   nullptr, sc, false, nullptr, e);
 }
 
 // Chebyshev-Jacobi on K_w (degree steps, diagonal dk), the updates fused into the divergence
@@ -908,9 +919,11 @@ void apply_wbfbt(Solver& s, Precond<T>& P, const T* r, T* z) {
   // middle product B C^-1 A D^-1 B^T
   launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.v1, nullptr, P.py, nullptr, nullptr, false,
                s.opwork);
-  launch_op<T>(st, F_A | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v1, P.v2, fine_mu(s, P), nullptr, nullptr, P.winv[1],
+  const T* sr = weight_scaling<T>(s, P, 1, P.v1);
+  launch_op<T>(st, F_A | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v1, P.v2, fine_mu(s, P), nullptr, nullptr, sr,
                false, s.opwork);
-  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, P.winv[0], false,
+  const T* sl = weight_scaling<T>(s, P, 0, P.v2);
+  launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, sl, false,
                nullptr);
   launch_remove_mean<T>(st, m.E, m.np, P.pm, s.red_partial, s.red_out + 2);
   apply_vcycle_K<T>(s, P, 0, P.pm, z);
@@ -1006,7 +1019,7 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   WB_REQUIRE(o.schur_sign == 1 || o.schur_sign == -1, WB_EINVAL, "schur_sign must be 1 or -1");
   WB_REQUIRE(o.assemble_mb >= 0.0, WB_EINVAL, "assemble_mb must be >= 0");
   WB_REQUIRE(o.schur_approx == 0 || o.schur_approx == 1, WB_EINVAL, "schur_approx must be 0 or 1");
-  WB_REQUIRE(o.weights == 0 || o.weights == 1, WB_EINVAL, "weights must be 0 or 1");
+  WB_REQUIRE(o.weights >= 0 && o.weights <= 2, WB_EINVAL, "weights must be 0, 1 or 2");
   WB_REQUIRE(o.precond_prec >= WB_FP64 && o.precond_prec <= WB_BF16X1, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
@@ -1073,17 +1086,38 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   alloc_work(s, P);
   P.mpinv = ar.alloc<double>((size_t)m.E * m.np);
   launch_pmass_inv(st, m.N, m.k, s.mu_q, P.mpinv);
+  // diag(A)-BFBT: the unmasked diag(A) and the unweighted lumped mass for its Poisson coefficient
+  const bool diag_a = o.weights == 2;
+  double *diag3 = nullptr, *mass1 = nullptr;
+  if (diag_a) {
+    diag3 = ar.alloc<double>((size_t)3 * m.nn);
+    launch_fill<double>(st, diag3, 0.0, (size_t)3 * m.nn);
+    launch_diag(st, 3, m.N, m.k, false, s.mu_q, diag3);
+    double* ones = ar.alloc<double>(m.nn);
+    launch_fill<double>(st, ones, 1.0, m.nn);
+    mass1 = ar.alloc<double>(m.nn);
+    launch_fill<double>(st, mass1, 0.0, m.nn);
+    launch_lumped_mass(st, m.N, m.k, 1.0, ones, mass1);
+  }
   for (int side = 0; side < 2; ++side) {
-    P.winv[side] = ar.alloc<double>(m.nn);
-    launch_fill<double>(st, P.winv[side], 0.0, m.nn);
-    if (o.weights == 1) launch_lumped_mass_grad(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
-    else launch_lumped_mass(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
-    launch_invert_diag(st, 1, m.N, m.k, false, P.winv[side]);
+    if (diag_a) {
+      // C^-1 = D^-1 = diag(A)^-1 per velocity DOF (the masked level-0 Jacobi inverse)
+      P.winv[side] = ar.alloc<double>((size_t)3 * m.nn);
+      WB_HIP(hipMemcpyAsync(P.winv[side], P.A.L[0].dinv, sizeof(double) * 3 * m.nn,
+                            hipMemcpyDeviceToDevice, st));
+    } else {
+      P.winv[side] = ar.alloc<double>(m.nn);
+      launch_fill<double>(st, P.winv[side], 0.0, m.nn);
+      if (o.weights == 1) launch_lumped_mass_grad(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
+      else launch_lumped_mass(st, m.N, m.k, amps[side], mu_nodes, P.winv[side]);
+      launch_invert_diag(st, 1, m.N, m.k, false, P.winv[side]);
+    }
     P.dk[side] = ar.alloc<double>((size_t)m.E * m.np);
-    launch_diag_K(st, m.N, m.k, dbh, P.winv[side], P.dk[side]);
+    launch_diag_K(st, m.N, m.k, dbh, P.winv[side], P.dk[side], diag_a);
     // Poisson hierarchy on the coefficient 1/w at the Gauss points (eq. 11, 12)
     double* cq = ar.alloc<double>((size_t)m.E * n3);
-    if (o.weights == 1) launch_poisson_coef_grad(st, m.N, m.k, amps[side], s.mu_q, mu_nodes, cq);
+    if (diag_a) launch_diag_a_coef(st, m.N, m.k, amps[side], diag3, mass1, cq);
+    else if (o.weights == 1) launch_poisson_coef_grad(st, m.N, m.k, amps[side], s.mu_q, mu_nodes, cq);
     else launch_poisson_coef(st, m.N, m.k, amps[side], s.mu_q, cq);
     build_hierarchy(s, P.Pois[side], 1, cq, side == 0 ? 2000 : 3000, est);
   }
@@ -1123,8 +1157,9 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     cast_hierarchy(s, P.A, F.A);
     for (int side = 0; side < 2; ++side) {
       cast_hierarchy(s, P.Pois[side], F.Pois[side]);
-      F.winv[side] = ar.alloc<float>(m.nn);
-      launch_cast<double, float>(st, m.nn, P.winv[side], F.winv[side]);
+      const size_t wl = (o.weights == 2 ? 3 : 1) * (size_t)m.nn;
+      F.winv[side] = ar.alloc<float>(wl);
+      launch_cast<double, float>(st, wl, P.winv[side], F.winv[side]);
       F.dk[side] = ar.alloc<float>((size_t)m.E * m.np);
       launch_cast<double, float>(st, (size_t)m.E * m.np, P.dk[side], F.dk[side]);
       F.klmin[side] = P.klmin[side];

@@ -9,7 +9,7 @@ python -m paper_1607_03936_amd.sweep [--N 32] [--k 2] [--max-iter 1000] [--json 
 --amp instead runs the boundary amplification study of Sec. 5 (Table 2): w-BFBT with
 a_l x a_r in {1, 2, 4, 8, 16, 32}^2 on S16 at DR 1e6 (or the given sinkers and ratio).
 --weights instead compares the w-BFBT weights sqrt(mu) and (mu^2 + |grad mu|^2)^(1/4) (the
-remark of Sec. 4) over the given sinkers and ratios.
+remark of Sec. 4) and diag(A)-BFBT (Sec. 4) over the given sinkers and ratios.
 
 Sinker sets: n in {1, 4, 8, 12, 16, 20, 24, 28}, centres from the seeded generator (seed 100 + n),
 delta 200, omega 0.1, beta 10, mu in [DR^-1/2, DR^1/2]; a_l = 1, a_r = max(1, (N/16) 2^(k-2)).
@@ -117,14 +117,15 @@ def weight_forms(a, sinkers, ratios):
             v = wb.Viscosity.sinker(m, c, 200.0, 0.1, dr ** -0.5, dr ** 0.5)
             wb.wb_rhs_sinker(m, c, 200.0, 0.1, 10.0, f)
             rec = {"sinkers": n, "dr": dr}
-            for label, wf in (("sqrt", 0), ("grad", 1)):
-                s = wb.Solver(m, v, a_l=1.0, a_r=a_r, weights=wf, max_iter=a.max_iter)
+            for label, wf in (("sqrt", 0), ("grad", 1), ("diagA", 2)):
+                amp_r = 1.0 if wf == 2 else a_r
+                s = wb.Solver(m, v, a_l=1.0, a_r=amp_r, weights=wf, max_iter=a.max_iter)
                 rep = s.solve(f, u, p, allow_noconv=True)
                 rec[label] = rep.iters if rep.rel_res <= 1e-6 else -rep.iters
                 del s
             rows.append(rec)
-            print(f"S{n}-rand DR {dr:.0e}: sqrt(mu) {abs(rec['sqrt'])}  gradient {abs(rec['grad'])}",
-                  flush=True)
+            print(f"S{n}-rand DR {dr:.0e}: w-BFBT sqrt(mu) {abs(rec['sqrt'])}  gradient {abs(rec['grad'])}"
+                  f"  diag(A)-BFBT {abs(rec['diagA'])}{'' if rec['diagA'] > 0 else ' (cap)'}", flush=True)
     if a.json:
         with open(a.json, "w") as fh:
             json.dump({"N": a.N, "k": a.k, "rows": rows}, fh, indent=1)

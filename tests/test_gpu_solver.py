@@ -357,3 +357,38 @@ def test_gradient_weights_match_oracle(name):
     b = np.concatenate([st.F, np.zeros(st.np_)])
     _, it_o, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
     assert abs(rep.iters - it_o) <= 2, (rep.iters, it_o)
+
+
+@pytest.mark.parametrize("name", ["n8k2", "n4k3"])
+def test_diag_a_bfbt_matches_oracle(name):
+    """diag(A)-BFBT (C = D = diag(A), Sec. 4): the per-DOF weights, the K_w diagonal, the Poisson
+    coefficient, the K_w V-cycle and the FGMRES count follow the oracle."""
+    wb = _wb()
+    w = SETUPS[name]
+    c = w.centers()
+    st = solver.Stokes(w.N, w.k, c, w.delta, w.omega, w.mu_min, w.mu_max, a_l=1.0, a_r=1.0,
+                       weights="diagA")
+    P = solver.Preconditioner(st)
+    om = st.mesh
+    m = wb.Mesh(w.N, w.k)
+    v = wb.Viscosity.sinker(m, c, w.delta, w.omega, w.mu_min, w.mu_max)
+    s = wb.Solver(m, v, a_l=1.0, a_r=1.0, weights=2)
+    assert _rel(host(s.query(0, 0, om.u_dof))[st.idx], st.Cinv) < 1e-13
+    assert _rel(host(s.query(4, 0, om.p_dof)), P.disc["l"][1]) < 1e-12
+    E, n3 = om.E, om.n ** 3
+    assert _rel(host(s.query(6, 0, E * n3)), P.Pl_mg.levels[0].coef.reshape(-1)) < 1e-13
+    r = st.remove_mean(random_vector(81, om.p_dof))
+    out = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    s.apply_K(0, dev(r), out)
+    assert _rel(host(out), st.Kl @ r) < 1e-12
+    s.vcycle_K(0, dev(r), out)
+    assert _rel(host(out), P.k_vcycle("l", r)) < 1e-9
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, c, w.delta, w.omega, w.beta, f)
+    u = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    p = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    rep = s.solve(f, u, p)
+    assert rep.rel_res <= 1e-6
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    _, it_o, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
+    assert abs(rep.iters - it_o) <= 2, (rep.iters, it_o)
