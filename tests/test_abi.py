@@ -58,3 +58,24 @@ def test_host_entry_points_without_gpu():
     assert L.wb_mesh_create(1025, 1, ctypes.byref(h)) == wb.WB_EINVAL
     assert L.wb_apply_A(None, None, None, None, None) == wb.WB_EINVAL
     assert L.wb_solve(None, None, None, None, None, None) == wb.WB_EINVAL
+
+
+def test_opts_struct_matches_header():
+    """The binding's wb_opts mirrors the header's field order and types, and the defaults of the
+    later options (graph replay, Schur sign and approximation, assembly limit, weights)."""
+    wb, L = _lib()
+    src = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} wb_opts;", src, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(int|double)\s+([\w\s,]+);", body)
+    names = []
+    for ty, decl in fields:
+        for nm in decl.split(","):
+            names.append((nm.strip(), ty))
+    ct = {"int": ctypes.c_int, "double": ctypes.c_double}
+    assert [(n, ct[t]) for n, t in names] == list(wb.wb_opts._fields_)
+    o = wb.opts()
+    assert (o.use_graph, o.schur_sign, o.schur_approx, o.weights) == (1, -1, 0, 0)
+    assert o.assemble_mb == 32.0
+    with pytest.raises(TypeError):
+        wb.opts(no_such_option=1)

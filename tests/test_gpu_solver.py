@@ -392,3 +392,15 @@ def test_diag_a_bfbt_matches_oracle(name):
     b = np.concatenate([st.F, np.zeros(st.np_)])
     _, it_o, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
     assert abs(rep.iters - it_o) <= 2, (rep.iters, it_o)
+
+
+def test_solver_rejects_invalid_options():
+    """Out-of-range options fail with WB_EINVAL and a message, and leave no solver behind."""
+    wb = _wb()
+    w, st, P, m, v, s = _pair("n8k2")
+    for kw, msg in ((dict(schur_approx=2), "schur_approx"), (dict(weights=3), "weights"),
+                    (dict(assemble_mb=-1.0), "assemble_mb"), (dict(schur_sign=0), "schur_sign"),
+                    (dict(lanczos_steps=5000), "lanczos_steps")):
+        with pytest.raises(wb.WbError) as ei:
+            wb.Solver(m, v, **kw)
+        assert ei.value.code == wb.WB_EINVAL and msg in str(ei.value), (kw, str(ei.value))
