@@ -70,7 +70,8 @@ typedef struct wb_solver wb_solver;
 typedef struct {
   double a_l, a_r;        /* Dirichlet boundary amplification of w_l, w_r (Sec. 5) */
   int cheb_degree;        /* Chebyshev-Jacobi steps per smoothing (3)              */
-  int lanczos_steps;      /* CG steps for the largest-eigenvalue estimate (10)     */
+  int lanczos_steps;      /* CG steps for the largest-eigenvalue estimate (10;
+                             1..100)                                              */
   int restart;            /* FGMRES restart length (100)                           */
   int max_iter;           /* FGMRES iteration cap (1000)                           */
   double rtol;            /* ||b - K x|| <= rtol ||b|| (1e-6)                      */

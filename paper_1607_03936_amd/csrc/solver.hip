@@ -1020,6 +1020,8 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   WB_REQUIRE(o.assemble_mb >= 0.0, WB_EINVAL, "assemble_mb must be >= 0");
   WB_REQUIRE(o.schur_approx == 0 || o.schur_approx == 1, WB_EINVAL, "schur_approx must be 0 or 1");
   WB_REQUIRE(o.weights >= 0 && o.weights <= 2, WB_EINVAL, "weights must be 0, 1 or 2");
+  WB_REQUIRE(o.lanczos_steps >= 1 && o.lanczos_steps <= 100, WB_EINVAL,
+             "lanczos_steps out of range (1..100)");
   WB_REQUIRE(o.precond_prec >= WB_FP64 && o.precond_prec <= WB_BF16X1, WB_EUNSUPPORTED,
              "preconditioner precision not built");
   const double t0 = now_s();
