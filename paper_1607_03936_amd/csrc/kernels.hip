@@ -943,6 +943,106 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
   }
 }
 
+// Gradient alone (B^T p) node by node.  On the uniform brick mesh every element carries the same
+// gradient matrix: the tensor product of the 1D integrals GM[a][i] = int P_a l_i and
+// GX[a][i] = int P_a l_i' (exact under the (k+1)-point Gauss rule), times -(h/2)^2 (eq. 2,
+// B = -div).  A velocity node therefore gathers the pressure modes of the at most eight elements
+// that contain it: no LDS, no face pass, every node written once.
+struct GradTab {
+  double GM[NMAX * NMAX], GX[NMAX * NMAX];  // [a n + i]
+};
+
+template <int n>
+constexpr GradTab build_gradtab() {
+  GradTab g{};
+  const Tables& t = CT<n>::t;
+  for (int a = 0; a < n - 1; ++a)
+    for (int i = 0; i < n; ++i) {
+      double m = 0.0, d = 0.0;
+      for (int q = 0; q < n; ++q) {
+        m += t.wg[q] * t.L[a * n + q] * t.B[q * n + i];
+        d += t.wg[q] * t.L[a * n + q] * t.D1[q * n + i];
+      }
+      g.GM[a * n + i] = m;
+      g.GX[a * n + i] = d;
+    }
+  return g;
+}
+
+template <int n>
+struct CG {
+  static constexpr GradTab t = build_gradtab<n>();
+};
+
+// One thread per node, all three components.  Per direction a node lies in one element (local
+// index 1..k-1) or, on an element boundary plane, in two (local index k in the lower, 0 in the
+// upper); an absent second candidate gets zero weights and repeats the first element's index, so
+// all eight combinations are loaded branch-free and in bounds.
+template <int n, typename T, bool DIR>
+__global__ void __launch_bounds__(256)
+k_grad_node(const int N, const int M, const int nn, const T hh, const T* __restrict__ p,
+            T* __restrict__ y, const int add) {
+  constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nn) return;
+  const int gc[3] = {g % M, (g / M) % M, g / (M * M)};
+  T val[3] = {T(0), T(0), T(0)};
+  const bool bnd = DIR && (gc[0] == 0 || gc[0] == M - 1 || gc[1] == 0 || gc[1] == M - 1 ||
+                           gc[2] == 0 || gc[2] == M - 1);
+  if (!bnd) {
+    int e0[3], e1[3];
+    T fm[3][2][k], fd[3][2][k];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int r = gc[d] % k, q = gc[d] / k;
+      const bool vert = r == 0;
+      const bool v0 = !vert || q > 0, v1 = vert && q < N;
+      const int i0 = vert ? k : r;
+      e0[d] = vert ? (q > 0 ? q - 1 : 0) : q;
+      e1[d] = v1 ? q : e0[d];
+#pragma unroll
+      for (int a = 0; a < k; ++a) {
+        T m0 = T(0), d0 = T(0);
+#pragma unroll
+        for (int ii = 1; ii <= k; ++ii) {
+          m0 = (i0 == ii) ? (T)CG<n>::t.GM[a * n + ii] : m0;
+          d0 = (i0 == ii) ? (T)CG<n>::t.GX[a * n + ii] : d0;
+        }
+        fm[d][0][a] = v0 ? m0 : T(0);
+        fd[d][0][a] = v0 ? d0 : T(0);
+        fm[d][1][a] = v1 ? (T)CG<n>::t.GM[a * n] : T(0);
+        fd[d][1][a] = v1 ? (T)CG<n>::t.GX[a * n] : T(0);
+      }
+    }
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+      for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+          const size_t e = (size_t)(sx ? e1[0] : e0[0]) +
+                           (size_t)N * ((sy ? e1[1] : e0[1]) + (size_t)N * (sz ? e1[2] : e0[2]));
+          const T* pe = p + e * NP;
+#pragma unroll
+          for (int m = 0; m < NP; ++m) {
+            const int a = CT<n>::t.ma[m], b = CT<n>::t.mb[m], c = CT<n>::t.mc[m];
+            const T pm = pe[m];
+            const T myz = fm[1][sy][b] * fm[2][sz][c];
+            val[0] += pm * (fd[0][sx][a] * myz);
+            val[1] += pm * (fm[0][sx][a] * fd[1][sy][b] * fm[2][sz][c]);
+            val[2] += pm * (fm[0][sx][a] * fm[1][sy][b] * fd[2][sz][c]);
+          }
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) val[c] *= -hh * hh;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t j = (size_t)c * nn + g;
+    y[j] = add ? y[j] + val[c] : val[c];
+  }
+}
+
 // Sum the partial values on internal brick planes into y (x planes, then y planes not on an
 // x plane, then z planes on neither).
 template <int n, int NC, typename T, bool DIR, int EP>
@@ -1046,6 +1146,10 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
     ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
     hipLaunchKernelGGL((k_op_gather<n, T, F, MF, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, N,
                        k, M, E, nn, hh, u, pout, sin, (int)add, ep);
+  } else if constexpr ((F & (F_A | F_B)) == 0 && NC == 3 && MF == 0 && EP == EPI_STORE) {
+    ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
+    hipLaunchKernelGGL((k_grad_node<n, T, (F & F_DIR) != 0>), dim3(grid_for(nn, 256)), dim3(256), 0,
+                       st, N, M, nn, hh, pin, y, (int)add);
   } else {
     constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY;
     const BrickGeom G = brick_geom(N, k, BX, BY);
