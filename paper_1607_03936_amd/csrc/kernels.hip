@@ -974,72 +974,199 @@ struct CG {
   static constexpr GradTab t = build_gradtab<n>();
 };
 
-// One thread per node, all three components.  Per direction a node lies in one element (local
+// Elements around a node coordinate g in one direction: the node lies in one element (local
 // index 1..k-1) or, on an element boundary plane, in two (local index k in the lower, 0 in the
-// upper); an absent second candidate gets zero weights and repeats the first element's index, so
-// all eight combinations are loaded branch-free and in bounds.
-template <int n, typename T, bool DIR>
+// upper).  The first candidate is e0 with weights GM/GX[.][i0], the second e1 with local index 0;
+// an absent candidate gets zero weights and repeats a valid element index, so loads stay in bounds.
+template <int n, typename T>
+__device__ __forceinline__ void node_cands(const int g, const int N, int& e0, int& e1,
+                                           T (&fm)[2][n - 1], T (&fd)[2][n - 1]) {
+  constexpr int k = n - 1;
+  const int r = g % k, q = g / k;
+  const bool vert = r == 0;
+  const bool v0 = !vert || q > 0, v1 = vert && q < N;
+  const int i0 = vert ? k : r;
+  e0 = vert ? (q > 0 ? q - 1 : 0) : q;
+  e1 = v1 ? q : e0;
+#pragma unroll
+  for (int a = 0; a < k; ++a) {
+    T m0 = T(0), d0 = T(0);
+#pragma unroll
+    for (int ii = 1; ii <= k; ++ii) {
+      m0 = (i0 == ii) ? (T)CG<n>::t.GM[a * n + ii] : m0;
+      d0 = (i0 == ii) ? (T)CG<n>::t.GX[a * n + ii] : d0;
+    }
+    fm[0][a] = v0 ? m0 : T(0);
+    fd[0][a] = v0 ? d0 : T(0);
+    fm[1][a] = v1 ? (T)CG<n>::t.GM[a * n] : T(0);
+    fd[1][a] = v1 ? (T)CG<n>::t.GX[a * n] : T(0);
+  }
+}
+
+// GM/GX[a][i] with a runtime local index i (selects over the compile-time table).
+template <int n, typename T>
+__device__ __forceinline__ void local_weights(const int i, T (&gm)[n - 1], T (&gx)[n - 1]) {
+#pragma unroll
+  for (int a = 0; a < n - 1; ++a) {
+    T m = T(0), d = T(0);
+#pragma unroll
+    for (int ii = 0; ii < n; ++ii) {
+      m = (i == ii) ? (T)CG<n>::t.GM[a * n + ii] : m;
+      d = (i == ii) ? (T)CG<n>::t.GX[a * n + ii] : d;
+    }
+    gm[a] = m;
+    gx[a] = d;
+  }
+}
+
+// Gradient with the Dirichlet mask, one thread per x-line segment: thread (ex, gy, gz) writes the
+// nodes gx = ex k .. ex k + k - 1 of the line (gy, gz), and the thread with ex = N - 1 also the
+// boundary node gx = M - 1.  The pressure modes of the elements around the line (x elements ex - 1
+// and ex, times the y and z candidates) are first contracted over y and z into Q[X][c][a] (x-mode
+// a, component c), shared by the k nodes; each node then takes a k-term sum per x element.
+template <int n, typename T>
 __global__ void __launch_bounds__(256)
-k_grad_node(const int N, const int M, const int nn, const T hh, const T* __restrict__ p,
+k_grad_line(const int N, const int M, const int nn, const T hh, const T* __restrict__ p,
             T* __restrict__ y, const int add) {
   constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nn) return;
-  const int gc[3] = {g % M, (g / M) % M, g / (M * M)};
-  T val[3] = {T(0), T(0), T(0)};
-  const bool bnd = DIR && (gc[0] == 0 || gc[0] == M - 1 || gc[1] == 0 || gc[1] == M - 1 ||
-                           gc[2] == 0 || gc[2] == M - 1);
-  if (!bnd) {
-    int e0[3], e1[3];
-    T fm[3][2][k], fd[3][2][k];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * M * M) return;
+  const int ex = t % N, gy = (t / N) % M, gz = t / (N * M);
+  T v[k][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int r = gc[d] % k, q = gc[d] / k;
-      const bool vert = r == 0;
-      const bool v0 = !vert || q > 0, v1 = vert && q < N;
-      const int i0 = vert ? k : r;
-      e0[d] = vert ? (q > 0 ? q - 1 : 0) : q;
-      e1[d] = v1 ? q : e0[d];
+  for (int i = 0; i < k; ++i)
 #pragma unroll
-      for (int a = 0; a < k; ++a) {
-        T m0 = T(0), d0 = T(0);
+    for (int c = 0; c < 3; ++c) v[i][c] = T(0);
+  if (gy > 0 && gy < M - 1 && gz > 0 && gz < M - 1) {
+    int y0, y1, z0, z1;
+    T fmy[2][k], fdy[2][k], fmz[2][k], fdz[2][k];
+    node_cands<n, T>(gy, N, y0, y1, fmy, fdy);
+    node_cands<n, T>(gz, N, z0, z1, fmz, fdz);
+    T Q[2][3][k];
 #pragma unroll
-        for (int ii = 1; ii <= k; ++ii) {
-          m0 = (i0 == ii) ? (T)CG<n>::t.GM[a * n + ii] : m0;
-          d0 = (i0 == ii) ? (T)CG<n>::t.GX[a * n + ii] : d0;
-        }
-        fm[d][0][a] = v0 ? m0 : T(0);
-        fd[d][0][a] = v0 ? d0 : T(0);
-        fm[d][1][a] = v1 ? (T)CG<n>::t.GM[a * n] : T(0);
-        fd[d][1][a] = v1 ? (T)CG<n>::t.GX[a * n] : T(0);
-      }
-    }
+    for (int X = 0; X < 2; ++X)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < k; ++a) Q[X][c][a] = T(0);
+    const int xl = ex > 0 ? ex - 1 : ex;
 #pragma unroll
     for (int sz = 0; sz < 2; ++sz)
 #pragma unroll
-      for (int sy = 0; sy < 2; ++sy)
+      for (int sy = 0; sy < 2; ++sy) {
+        const size_t row = (size_t)N * ((sy ? y1 : y0) + (size_t)N * (sz ? z1 : z0));
 #pragma unroll
-        for (int sx = 0; sx < 2; ++sx) {
-          const size_t e = (size_t)(sx ? e1[0] : e0[0]) +
-                           (size_t)N * ((sy ? e1[1] : e0[1]) + (size_t)N * (sz ? e1[2] : e0[2]));
-          const T* pe = p + e * NP;
+        for (int X = 0; X < 2; ++X) {
+          const T* pe = p + (row + (X ? ex : xl)) * NP;
 #pragma unroll
           for (int m = 0; m < NP; ++m) {
             const int a = CT<n>::t.ma[m], b = CT<n>::t.mb[m], c = CT<n>::t.mc[m];
             const T pm = pe[m];
-            const T myz = fm[1][sy][b] * fm[2][sz][c];
-            val[0] += pm * (fd[0][sx][a] * myz);
-            val[1] += pm * (fm[0][sx][a] * fd[1][sy][b] * fm[2][sz][c]);
-            val[2] += pm * (fm[0][sx][a] * fm[1][sy][b] * fd[2][sz][c]);
+            Q[X][0][a] += pm * (fmy[sy][b] * fmz[sz][c]);
+            Q[X][1][a] += pm * (fdy[sy][b] * fmz[sz][c]);
+            Q[X][2][a] += pm * (fmy[sy][b] * fdz[sz][c]);
           }
         }
+      }
+    const T h2 = -hh * hh;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) val[c] *= -hh * hh;
+    for (int i = 0; i < k; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < k; ++a) {
+          acc += Q[1][c][a] * (T)(c == 0 ? CG<n>::t.GX[a * n + i] : CG<n>::t.GM[a * n + i]);
+          if (i == 0) acc += Q[0][c][a] * (T)(c == 0 ? CG<n>::t.GX[a * n + k] : CG<n>::t.GM[a * n + k]);
+        }
+        v[i][c] = (i == 0 && ex == 0) ? T(0) : acc * h2;
+      }
   }
+  const size_t base = (size_t)ex * k + (size_t)M * (gy + (size_t)M * gz);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const size_t j = (size_t)c * nn + g;
-    y[j] = add ? y[j] + val[c] : val[c];
+#pragma unroll
+    for (int i = 0; i < k; ++i) {
+      const size_t j = (size_t)c * nn + base + i;
+      y[j] = add ? y[j] + v[i][c] : v[i][c];
+    }
+    if (ex == N - 1) {
+      const size_t j = (size_t)c * nn + base + k;
+      y[j] = add ? y[j] : T(0);
+    }
+  }
+}
+
+// Divergence with the Dirichlet mask (and an optional per-node input scaling), one lane per
+// element x-line: lane r of element e takes the nodes (i, j = r % n, l = r / n), i = 0..k,
+// contracts them in x into R_c[a] and multiplies by its y and z weights into a partial of every
+// mode; the n^2 partials of each mode are summed in LDS in lane order and go out through the
+// epilogue (pressure outputs e n_p + m).
+template <int n, typename T, int EP>
+__global__ void __launch_bounds__(256)
+k_div_line(const int N, const int M, const int E, const int nn, const T hh,
+           const T* __restrict__ u, const T* __restrict__ sin_, T* __restrict__ pout,
+           const int add, const Epi<T> ep) {
+  constexpr int k = n - 1, NN = n * n, NP = (n - 1) * n * (n + 1) / 6;
+  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW;
+  __shared__ T red[(SLOTS + 1) * NP * NN];
+  int slot, r;
+  bool lane_ok;
+  WaveMap<n>::map(threadIdx.x, slot, r, lane_ok);
+  const int e = blockIdx.x * SLOTS + slot;
+  const bool valid = lane_ok && e < E;
+  const int ee = valid ? e : 0;
+  const int ex = ee % N, ey = (ee / N) % N, ez = ee / (N * N);
+  const int j = r % n, l = r / n;
+  const int gy = ey * k + j, gz = ez * k + l;
+  T part[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) part[m] = T(0);
+  if (valid && gy > 0 && gy < M - 1 && gz > 0 && gz < M - 1) {
+    const size_t gyz = (size_t)M * (gy + (size_t)M * gz);
+    T uv[n][3], sv[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const size_t gn = (size_t)ex * k + i + gyz;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uv[i][c] = u[(size_t)c * nn + gn];
+      sv[i] = sin_ != nullptr ? sin_[gn] : T(1);
+    }
+    T R[3][k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < k; ++a) R[c][a] = T(0);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const int gx = ex * k + i;
+      const T s = (gx > 0 && gx < M - 1) ? sv[i] : T(0);
+#pragma unroll
+      for (int a = 0; a < k; ++a) {
+        const T mi = (T)CG<n>::t.GM[a * n + i], di = (T)CG<n>::t.GX[a * n + i];
+        R[0][a] += di * (s * uv[i][0]);
+        R[1][a] += mi * (s * uv[i][1]);
+        R[2][a] += mi * (s * uv[i][2]);
+      }
+    }
+    T gmj[k], gxj[k], gml[k], gxl[k];
+    local_weights<n, T>(j, gmj, gxj);
+    local_weights<n, T>(l, gml, gxl);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      const int a = CT<n>::t.ma[m], b = CT<n>::t.mb[m], c = CT<n>::t.mc[m];
+      part[m] = R[0][a] * (gmj[b] * gml[c]) + R[1][a] * (gxj[b] * gml[c]) + R[2][a] * (gmj[b] * gxl[c]);
+    }
+  }
+  T* rs = red + (lane_ok ? slot : SLOTS) * NP * NN;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) rs[m * NN + r] = part[m];
+  wave_sync();
+  if (valid && r < NP) {
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < NN; ++q) acc += rs[r * NN + q];
+    emit<EP>(ep, (size_t)e * NP + r, -hh * hh * acc, pout, add);
   }
 }
 
@@ -1144,12 +1271,17 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
   if constexpr ((F & (F_A | F_BT)) == 0) {
     constexpr int SLOTS = 4 * WaveMap<n>::EPW;
     ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
-    hipLaunchKernelGGL((k_op_gather<n, T, F, MF, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, N,
-                       k, M, E, nn, hh, u, pout, sin, (int)add, ep);
-  } else if constexpr ((F & (F_A | F_B)) == 0 && NC == 3 && MF == 0 && EP == EPI_STORE) {
+    if constexpr (MF == 0 && (F & F_DIR) != 0)
+      hipLaunchKernelGGL((k_div_line<n, T, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, N, M, E,
+                         nn, hh, u, sin, pout, (int)add, ep);
+    else
+      hipLaunchKernelGGL((k_op_gather<n, T, F, MF, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st,
+                         N, k, M, E, nn, hh, u, pout, sin, (int)add, ep);
+  } else if constexpr ((F & (F_A | F_B)) == 0 && (F & F_DIR) != 0 && NC == 3 && MF == 0 &&
+                       EP == EPI_STORE) {
     ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
-    hipLaunchKernelGGL((k_grad_node<n, T, (F & F_DIR) != 0>), dim3(grid_for(nn, 256)), dim3(256), 0,
-                       st, N, M, nn, hh, pin, y, (int)add);
+    hipLaunchKernelGGL((k_grad_line<n, T>), dim3(grid_for((size_t)N * M * M, 256)), dim3(256), 0, st,
+                       N, M, nn, hh, pin, y, (int)add);
   } else {
     constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY;
     const BrickGeom G = brick_geom(N, k, BX, BY);
