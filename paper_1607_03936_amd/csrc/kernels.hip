@@ -1524,11 +1524,12 @@ k_stencil(const int M, const T* __restrict__ S, const T* __restrict__ u, T* __re
 // Coarse tail of a scalar (Neumann) V-cycle in one workgroup: Chebyshev-Jacobi smoothing on an
 // assembled Q1 level of at most TAIL_MAX nodes, residual, restriction (linear 2:1), the coarsest
 // dense solve, prolongation and post-smoothing, with every vector in LDS and thread t owning
-// node t (its 27 stencil entries held in registers).  The steps and their arithmetic are those of
-// the per-kernel path (k_cheb_first, k_stencil with its epilogues, k_lin21, k_dense).
+// node t (its 27 stencil entries held in registers).  The steps are those of the per-kernel path
+// (k_cheb_first, k_stencil with its epilogues, k_lin21, k_dense); the coarsest product sums each
+// row over eight lanes instead of a wavefront, so it differs from k_dense by rounding order.
 template <typename T>
-__device__ inline T tail_apply(const int M, const int t, const T (&sr)[27], const T* v) {
-  const int ix = t % M, iy = (t / M) % M, iz = t / (M * M);
+__device__ inline T tail_apply(const int M, const int t, const int ix, const int iy, const int iz,
+                               const T (&sr)[27], const T* v) {
   T acc = T(0);
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
@@ -1547,6 +1548,7 @@ k_vcycle_tail(const TailArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg)
   __shared__ T b[TAIL_MAX], x[TAIL_MAX], r[TAIL_MAX], dv[2][TAIL_MAX], bc[TAIL_MAX], xc[TAIL_MAX];
   const int t = threadIdx.x, M = a.M, nn = M * M * M, Mc = a.Mc, nc = Mc * Mc * Mc;
   const bool own = t < nn;
+  const int tt = own ? t : 0, ix = tt % M, iy = (tt / M) % M, iz = tt / (M * M);
   T sr[27];
 #pragma unroll
   for (int o = 0; o < 27; ++o) sr[o] = own ? a.S[(size_t)o * nn + t] : T(0);
@@ -1563,7 +1565,7 @@ k_vcycle_tail(const TailArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg)
   }
   __syncthreads();
   for (int it = 1; it < a.deg; ++it) {
-    const T v = tail_apply<T>(M, own ? t : 0, sr, dv[cur]);
+    const T v = tail_apply<T>(M, tt, ix, iy, iz, sr, dv[cur]);
     if (own) {
       const T ri = r[t] - v;
       const T dn = a.alpha[it] * dv[cur][t] + a.beta[it] * dinv * ri;
@@ -1576,7 +1578,7 @@ k_vcycle_tail(const TailArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg)
   }
   // residual and restriction
   {
-    const T v = tail_apply<T>(M, own ? t : 0, sr, x);
+    const T v = tail_apply<T>(M, tt, ix, iy, iz, sr, x);
     if (own) r[t] = b[t] - v;
   }
   __syncthreads();
@@ -1607,8 +1609,35 @@ k_vcycle_tail(const TailArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg)
     bc[t] = (T)s;
   }
   __syncthreads();
-  // coarsest: xc[idx[row]] = sum_c G[row, c] bc[idx[c]], one wavefront per row
-  {
+  // coarsest: xc[idx[row]] = sum_c G[row, c] bc[idx[c]]
+  // eight lanes per row (row t / 8), lane t % 8 holding columns t % 8 + 8 c, all loads of a lane
+  // issued together
+  constexpr int GCH = 16;
+  const bool gfast = a.nd <= TAIL_THREADS / 8 && a.nd <= 8 * GCH;
+  const int grow = t >> 3, gpart = t & 7;
+  const bool grow_ok = gfast && grow < a.nd;
+  double gv[GCH];
+#pragma unroll
+  for (int c = 0; c < GCH; ++c) {
+    const int col = gpart + 8 * c;
+    gv[c] = (grow_ok && col < a.nd) ? a.G[(size_t)grow * a.nd + col] : 0.0;
+  }
+  const int grow_dst = grow_ok ? a.gidx[grow] : 0;
+  const int gsel = (gfast && t < a.nd) ? a.gidx[t] : 0;
+  if (gfast) {
+    // gather the right-hand side in row order into r (free until the post-smoothing)
+    if (t < a.nd) r[t] = bc[gsel];
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < GCH; ++c) {
+      const int col = gpart + 8 * c;
+      if (col < a.nd) s += gv[c] * (double)r[col];
+    }
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (grow_ok && gpart == 0) xc[grow_dst] = (T)s;
+  } else {
     const int lane = t & 63, wave = t >> 6;
     for (int row = wave; row < a.nd; row += TAIL_THREADS / 64) {
       double s = 0.0;
@@ -1635,7 +1664,7 @@ k_vcycle_tail(const TailArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg)
   // post-smoothing from x: the first correction is added to x by the next step
   cur = 0;
   {
-    const T v = tail_apply<T>(M, own ? t : 0, sr, x);
+    const T v = tail_apply<T>(M, tt, ix, iy, iz, sr, x);
     if (own) {
       const T ri = b[t] - v;
       r[t] = ri;
@@ -1645,7 +1674,7 @@ k_vcycle_tail(const TailArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg)
   __syncthreads();
   bool pending = true;
   for (int it = 1; it < a.deg; ++it) {
-    const T v = tail_apply<T>(M, own ? t : 0, sr, dv[cur]);
+    const T v = tail_apply<T>(M, tt, ix, iy, iz, sr, dv[cur]);
     if (own) {
       const T ri = r[t] - v;
       const T d0 = dv[cur][t];
