@@ -154,7 +154,8 @@ struct Rows1D {
 template <typename T>
 void launch_kron(hipStream_t st, const Rows1D& R, int NC, bool dir, bool add, const T* in, T* out);
 
-// Element-wise L2 projection Q_k -> P_{k-1} (gather) and its transpose (scatter-add).
+// Element-wise L2 projection Q_k -> P_{k-1} (p = I u, or p += I u with add) and its transpose
+// u = I^T p (u overwritten on every node).
 template <typename T>
 void launch_modal_I(hipStream_t st, int N, int k, const T* u, T* p, bool add);
 template <typename T>

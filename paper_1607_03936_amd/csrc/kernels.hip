@@ -2053,21 +2053,76 @@ __global__ void k_modal_I(const KT<n, T> tb, int N, int k, int M, int E, const T
   p[idx] = add ? p[idx] + s : s;
 }
 
+// Transpose of the element-wise projection onto the Legendre modes, u = I^T p on the continuous
+// Q_k nodes (no boundary mask), gathered node by node: thread (ex, gy, gz) writes the nodes
+// gx = ex k .. ex k + k - 1 of the line (gy, gz) and the thread with ex = N - 1 also gx = M - 1.
+// The modes of the elements around the line are contracted over y and z first (J weights of the
+// y and z candidates), then each node takes a k-term sum per neighbouring x element.
 template <int n, typename T>
-__global__ void k_modal_IT(const KT<n, T> tb, int N, int k, int M, int E, const T* __restrict__ p,
-                           T* __restrict__ u) {
-  constexpr int NN = n * n, N3 = NN * n, NP = (n - 1) * n * (n + 1) / 6;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)E * N3) return;
-  const int e = (int)(idx / N3), li = (int)(idx % N3);
-  const int a = li % n, b = (li / n) % n, c = li / NN;
-  const int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
-  T s = T(0);
-  for (int m = 0; m < NP; ++m)
-    s += tb.J[tb.ma[m] * n + a] * tb.J[tb.mb[m] * n + b] * tb.J[tb.mc[m] * n + c] *
-         p[(size_t)e * NP + m];
-  const int g = (ex * k + a) + M * ((ey * k + b) + M * (ez * k + c));
-  atomic_add(&u[g], s);
+__global__ void __launch_bounds__(256)
+k_modal_IT(const int N, const int M, const T* __restrict__ p, T* __restrict__ u) {
+  constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * M * M) return;
+  const int ex = t % N, gy = (t / N) % M, gz = t / (N * M);
+  int yc[2], zc[2];
+  T jy[2][k], jz[2][k];
+  const int gc[2] = {gy, gz};
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const int r = gc[d] % k, q = gc[d] / k;
+    const bool vert = r == 0;
+    const bool v0 = !vert || q > 0, v1 = vert && q < N;
+    const int i0 = vert ? k : r;
+    const int e0 = vert ? (q > 0 ? q - 1 : 0) : q;
+    (d ? zc : yc)[0] = e0;
+    (d ? zc : yc)[1] = v1 ? q : e0;
+#pragma unroll
+    for (int a = 0; a < k; ++a) {
+      T w0 = T(0);
+#pragma unroll
+      for (int ii = 1; ii <= k; ++ii) w0 = (i0 == ii) ? (T)CT<n>::t.J[a * n + ii] : w0;
+      (d ? jz : jy)[0][a] = v0 ? w0 : T(0);
+      (d ? jz : jy)[1][a] = v1 ? (T)CT<n>::t.J[a * n] : T(0);
+    }
+  }
+  T Q[2][k];
+#pragma unroll
+  for (int X = 0; X < 2; ++X)
+#pragma unroll
+    for (int a = 0; a < k; ++a) Q[X][a] = T(0);
+  const int xl = ex > 0 ? ex - 1 : ex;
+#pragma unroll
+  for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {
+      const size_t row = (size_t)N * (yc[sy] + (size_t)N * zc[sz]);
+#pragma unroll
+      for (int X = 0; X < 2; ++X) {
+        const T* pe = p + (row + (X ? ex : xl)) * NP;
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+          Q[X][CT<n>::t.ma[m]] += pe[m] * (jy[sy][CT<n>::t.mb[m]] * jz[sz][CT<n>::t.mc[m]]);
+      }
+    }
+  const T lo = ex > 0 ? T(1) : T(0);
+  const size_t base = (size_t)ex * k + (size_t)M * (gy + (size_t)M * gz);
+#pragma unroll
+  for (int i = 0; i < k; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < k; ++a) {
+      acc += Q[1][a] * (T)CT<n>::t.J[a * n + i];
+      if (i == 0) acc += lo * Q[0][a] * (T)CT<n>::t.J[a * n + k];
+    }
+    u[base + i] = acc;
+  }
+  if (ex == N - 1) {
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < k; ++a) acc += Q[1][a] * (T)CT<n>::t.J[a * n + k];
+    u[base + k] = acc;
+  }
 }
 
 __global__ void k_coarsen_p(int E, int nf, int nc, const double* __restrict__ Q,
@@ -2655,11 +2710,10 @@ void launch_modal_I(hipStream_t st, int N, int k, const T* u, T* p, bool add) {
 }
 template <typename T>
 void launch_modal_IT(hipStream_t st, int N, int k, const T* p, T* u) {
-  const int M = k * N + 1, E = N * N * N, n3 = (k + 1) * (k + 1) * (k + 1);
+  const int M = k * N + 1;
   WB_BY_ORDER(k, {
-    auto tb = make_kt<n, T>(k);
-    hipLaunchKernelGGL((k_modal_IT<n, T>), dim3(grid_for((size_t)E * n3, 256)), dim3(256), 0, st, tb,
-                       N, k, M, E, p, u);
+    hipLaunchKernelGGL((k_modal_IT<n, T>), dim3(grid_for((size_t)N * M * M, 256)), dim3(256), 0, st,
+                       N, M, p, u);
   });
 }
 template void launch_modal_I<double>(hipStream_t, int, int, const double*, double*, bool);

@@ -900,7 +900,6 @@ void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* b, T* x) {
   apply_K_epi<T>(s, P, side, x, res);
   Hierarchy<T>& H = P.Pois[side];
   Level<T>& L0 = H.L[0];
-  launch_fill<T>(st, L0.b, T(0), L0.len);
   launch_modal_IT<T>(st, m.N, m.k, P.pr, L0.b);
   vcycle<T>(s, H, 0, L0.b, L0.x);
   launch_modal_I<T>(st, m.N, m.k, L0.x, x, true);
