@@ -7,6 +7,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
+#include <exception>
 
 #include "solver.h"
 
@@ -125,36 +127,47 @@ double now_s() {
 }
 
 // ---------------------------------------------------------------- host linear algebra
-// In-place inverse of an SPD matrix via Cholesky (n small).
+// In-place inverse of an SPD matrix (n small): Cholesky A = L L^T, W = L^-1 by forward
+// substitution, A^-1 = W^T W accumulated row by row of W (all inner loops contiguous).
 void spd_inverse(std::vector<double>& A, int n) {
   std::vector<double> Lm(A);
   for (int j = 0; j < n; ++j) {
-    double s = Lm[j * n + j];
-    for (int p = 0; p < j; ++p) s -= Lm[j * n + p] * Lm[j * n + p];
+    double s = Lm[(size_t)j * n + j];
+    for (int p = 0; p < j; ++p) s -= Lm[(size_t)j * n + p] * Lm[(size_t)j * n + p];
     if (!(s > 0.0)) throw Error{WB_ENAN, "coarse operator is not positive definite"};
     const double d = std::sqrt(s);
-    Lm[j * n + j] = d;
+    Lm[(size_t)j * n + j] = d;
     for (int i = j + 1; i < n; ++i) {
-      double t = Lm[i * n + j];
-      for (int p = 0; p < j; ++p) t -= Lm[i * n + p] * Lm[j * n + p];
-      Lm[i * n + j] = t / d;
+      double t = Lm[(size_t)i * n + j];
+      for (int p = 0; p < j; ++p) t -= Lm[(size_t)i * n + p] * Lm[(size_t)j * n + p];
+      Lm[(size_t)i * n + j] = t / d;
     }
   }
-  // solve for each unit vector
-  std::vector<double> col(n);
-  for (int c = 0; c < n; ++c) {
-    for (int i = 0; i < n; ++i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int p = 0; p < i; ++p) t -= Lm[i * n + p] * col[p];
-      col[i] = t / Lm[i * n + i];
+  // W = L^-1 (lower triangular): row i from the rows above it
+  std::vector<double> W((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double* wi = &W[(size_t)i * n];
+    wi[i] = 1.0;
+    for (int p = 0; p < i; ++p) {
+      const double l = Lm[(size_t)i * n + p];
+      const double* wp = &W[(size_t)p * n];
+      for (int c = 0; c <= p; ++c) wi[c] -= l * wp[c];
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double t = col[i];
-      for (int p = i + 1; p < n; ++p) t -= Lm[p * n + i] * col[p];
-      col[i] = t / Lm[i * n + i];
-    }
-    for (int i = 0; i < n; ++i) A[i * n + c] = col[i];
+    const double inv = 1.0 / Lm[(size_t)i * n + i];
+    for (int c = 0; c <= i; ++c) wi[c] *= inv;
   }
+  // A^-1 = W^T W: lower triangle by rank-one updates with the rows of W, then mirrored
+  std::fill(A.begin(), A.end(), 0.0);
+  for (int p = 0; p < n; ++p) {
+    const double* wp = &W[(size_t)p * n];
+    for (int i = 0; i <= p; ++i) {
+      const double wi = wp[i];
+      double* ai = &A[(size_t)i * n];
+      for (int j = 0; j <= i; ++j) ai[j] += wi * wp[j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) A[(size_t)j * n + i] = A[(size_t)i * n + j];
 }
 
 // Largest eigenvalue of a symmetric tridiagonal matrix (cyclic Jacobi on the dense form).
@@ -577,12 +590,14 @@ void build_hierarchy(Solver& s, Hierarchy<double>& H, int NC, const double* coef
 }
 
 // Coarsest level: dense inverse (velocity: interior DOFs, SPD) or pseudo-inverse (Poisson,
-// Neumann), from its stencil Sh (host copy).
-void coarsest_inverse(Solver& s, Hierarchy<double>& H, const std::vector<double>& Sh,
-                      std::vector<std::vector<double>>& keep_d, std::vector<std::vector<int>>& keep_i) {
-  hipStream_t st = s.st;
-  Arena& ar = s.arena;
-  Level<double>& C = H.L.back();
+// Neumann), from its stencil Sh (host copy); coarsest_upload puts it on the device.
+struct CoarseDense {
+  std::vector<double> G;  // [nd][nd]
+  std::vector<int> idx;   // level DOF of row r
+};
+
+// Host part, touching no device state (the three hierarchies' inverses run on host threads).
+CoarseDense coarsest_dense(const Level<double>& C, const std::vector<double>& Sh) {
   const int NC = C.NC;
   const int M = C.k * C.N + 1;
   std::vector<int> idx;
@@ -634,12 +649,21 @@ void coarsest_inverse(Solver& s, Hierarchy<double>& H, const std::vector<double>
     for (int i = 0; i < nd; ++i)
       for (int j = 0; j < nd; ++j) Ad[(size_t)i * nd + j] += -rm[i] - cm[j] + tm;
   }
+  return CoarseDense{std::move(Ad), std::move(idx)};
+}
+
+void coarsest_upload(Solver& s, Hierarchy<double>& H, CoarseDense&& cd,
+                     std::vector<std::vector<double>>& keep_d, std::vector<std::vector<int>>& keep_i) {
+  hipStream_t st = s.st;
+  Arena& ar = s.arena;
+  Level<double>& C = H.L.back();
+  const int nd = (int)cd.idx.size();
   H.nd = nd;
   H.G = ar.alloc<double>((size_t)nd * nd);
   H.gidx = ar.alloc<int>(nd);
   // the host buffers stay alive (keep_*) until the caller has synchronized the stream
-  keep_d.push_back(std::move(Ad));
-  keep_i.push_back(std::move(idx));
+  keep_d.push_back(std::move(cd.G));
+  keep_i.push_back(std::move(cd.idx));
   WB_HIP(hipMemcpyAsync(H.G, keep_d.back().data(), sizeof(double) * keep_d.back().size(),
                         hipMemcpyHostToDevice, st));
   WB_HIP(hipMemcpyAsync(H.gidx, keep_i.back().data(), sizeof(int) * nd, hipMemcpyHostToDevice, st));
@@ -1148,7 +1172,24 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
     finish_setup_estimates(s, est, h);
     std::vector<std::vector<double>> keep_d;
     std::vector<std::vector<int>> keep_i;
-    for (int i = 0; i < 3; ++i) coarsest_inverse(s, *hs[i], Sh[i], keep_d, keep_i);
+    // the three dense inverses on host threads, then their uploads in order
+    CoarseDense cd[3];
+    std::exception_ptr err[3];
+    {
+      std::vector<std::thread> th;
+      for (int i = 0; i < 3; ++i)
+        th.emplace_back([&, i] {
+          try {
+            cd[i] = coarsest_dense(hs[i]->L.back(), Sh[i]);
+          } catch (...) {
+            err[i] = std::current_exception();
+          }
+        });
+      for (auto& t : th) t.join();
+    }
+    for (int i = 0; i < 3; ++i)
+      if (err[i]) std::rethrow_exception(err[i]);
+    for (int i = 0; i < 3; ++i) coarsest_upload(s, *hs[i], std::move(cd[i]), keep_d, keep_i);
     WB_HIP(hipStreamSynchronize(st));
   }
   clk.mark("estimates + coarsest inverses");
