@@ -188,3 +188,41 @@ def test_apply_A_full_size_sampled_rows(name):
     scale = np.abs(want).max()
     assert np.abs(got[dofs] - want).max() <= 1e-12 * scale
     assert np.all(got[om.vel_boundary] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["c2", "c5"])
+def test_apply_B_BT_full_size_sampled_rows(name):
+    # the divergence and gradient at the workload sizes (their launch shapes at full size),
+    # checked on sampled elements and velocity DOFs computed element by element by the oracle
+    wb = _wb()
+    w = WORKLOADS[name]
+    m = wb.Mesh(w.N, w.k)
+    om = fem.Mesh(w.N, w.k)
+    n3, npm = om.n ** 3, om.n_p
+    Be = fem.element_div(w.k, om.h)
+    u = random_vector(21, om.u_dof)
+    u[om.vel_boundary] = 0.0
+    p = random_vector(22, om.p_dof)
+    pg = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    wb.wb_apply_B(m, dev(u), pg)
+    ug = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    wb.wb_apply_BT(m, dev(p), ug)
+    got_p, got_u = host(pg), host(ug)
+
+    rng = np.random.default_rng(23)
+    els = np.concatenate([rng.choice(om.E, 200, replace=False), [0, 1, om.E - 2, om.E - 1]])
+    for e in els:
+        gd = np.concatenate([c * om.n_nodes + om.elem_nodes[e] for c in range(3)])
+        want = Be @ u[gd]
+        assert np.abs(got_p[e * npm:(e + 1) * npm] - want).max() <= 1e-12 * np.abs(want).max()
+
+    interior = om.vel_interior
+    dofs = np.concatenate([rng.choice(interior, 200, replace=False), interior[:3], interior[-3:]])
+    want = np.zeros(len(dofs))
+    for t, d in enumerate(dofs):
+        c, g = divmod(int(d), om.n_nodes)
+        for e in fem.elements_of_node(om, g):
+            li = int(np.flatnonzero(om.elem_nodes[e] == g)[0])
+            want[t] += Be[:, c * n3 + li] @ p[e * npm:(e + 1) * npm]
+    assert np.abs(got_u[dofs] - want).max() <= 1e-12 * np.abs(want).max()
+    assert np.all(got_u[om.vel_boundary] == 0.0)
