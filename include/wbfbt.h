@@ -57,7 +57,8 @@ typedef enum {
  * tensor contraction of the element operators on the BF16 matrix cores with FP32 accumulation,
  * table and line each split into BF16 high and low parts (three products, about 2^-16 relative
  * error per contraction).  WB_BF16X1: the same with a single product of BF16-rounded operands
- * (about 2^-8 per contraction). */
+ * (about 2^-8 per contraction).  The two BF16 forms are built for k <= 4 (WB_EUNSUPPORTED for
+ * k = 5). */
 typedef enum { WB_FP64 = 0, WB_FP32 = 1, WB_BF16 = 2, WB_BF16X1 = 3 } wb_prec;
 
 typedef struct wb_mesh wb_mesh;
@@ -120,7 +121,7 @@ WB_API void wb_opts_default(wb_opts* o);
 WB_API const char* wb_last_error(void);
 
 /* ---- mesh (Sec. 1.2): uniform N^3 hexahedra of the unit cube, order k ---- */
-/* N >= 1, 1 <= k <= 4.  Creates structured metadata only (no device memory). */
+/* N >= 1, 1 <= k <= 5.  Creates structured metadata only (no device memory). */
 WB_API wb_status wb_mesh_create(int N, int k, wb_mesh** out);
 WB_API void wb_mesh_destroy(wb_mesh* m);
 /* n_nodes = (kN+1)^3, n_elem = N^3, n_p = k(k+1)(k+2)/6. Any output may be NULL. */
@@ -170,7 +171,8 @@ WB_API wb_status wb_apply_A_lowp(const wb_mesh* m, const wb_visc* v, int prec, c
 /* ---- solver: w-BFBT (eq. 8, Sec. 5) + p/h-multigrid (Sec. 6) + FGMRES (eq. 3) ----
  * Builds the velocity multigrid hierarchy, the weights C = M(w_l), D = M(w_r),
  * w = a sqrt(mu), the two pressure-Poisson hierarchies and the Krylov space.
- * opts may be NULL (defaults).  Synchronizes `stream`. */
+ * opts may be NULL (defaults).  Synchronizes `stream`.  Needs 2 <= k <= 5 (WB_EUNSUPPORTED
+ * otherwise). */
 WB_API wb_status wb_solver_create(const wb_mesh* m, const wb_visc* v, const wb_opts* opts,
                                   void* stream, wb_solver** out);
 WB_API void wb_solver_destroy(wb_solver* s);

@@ -40,7 +40,7 @@ void check_launch() {
 
 Mesh make_mesh(int N, int k) {
   WB_REQUIRE(N >= 1 && N <= 1024, WB_EINVAL, "N must be in [1, 1024]");
-  WB_REQUIRE(k >= 1 && k <= 4, WB_EUNSUPPORTED, "k must be in [1, 4]");
+  WB_REQUIRE(k >= 1 && k <= 5, WB_EUNSUPPORTED, "k must be in [1, 5]");
   Mesh m;
   m.N = N;
   m.k = k;

@@ -273,6 +273,7 @@ template <int ES> struct Lds<3, ES> { static constexpr int SY = 3, SZ = 9, SL = 
 template <> struct Lds<4, 8> { static constexpr int SY = 4, SZ = 19, SL = 88; };
 template <> struct Lds<4, 4> { static constexpr int SY = 4, SZ = 18, SL = 71; };
 template <int ES> struct Lds<5, ES> { static constexpr int SY = 5, SZ = 25, SL = 125; };
+template <int ES> struct Lds<6, ES> { static constexpr int SY = 6, SZ = 37, SL = 222; };
 
 // Element computation shared by the operator kernels.  The n^2 lanes of an element take three
 // roles, always with a = r % n, b = r / n: the z-line (a, b, .), the y-line (a, ., b) or the
@@ -718,6 +719,7 @@ template <> struct Tile<2> { static constexpr int BX = 8, BY = 8; };
 template <> struct Tile<3> { static constexpr int BX = 8, BY = 4; };
 template <> struct Tile<4> { static constexpr int BX = 8, BY = 4; };
 template <> struct Tile<5> { static constexpr int BX = 4, BY = 4; };
+template <> struct Tile<6> { static constexpr int BX = 4, BY = 2; };
 
 struct BrickGeom {
   int N, k, M, nn, E;
@@ -1344,9 +1346,23 @@ void op_dispatch_mf(hipStream_t st, int flags, int NC, int N, int k, const T* u,
       case F_A | F_DIR:
         return op_launch<n, 3, T, F_A | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
       case F_A | F_BT | F_B | F_DIR:
-        if constexpr (MF == 0)
-          return op_launch<n, 3, T, F_A | F_BT | F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout,
-                                                                  sin, add, work, ep);
+        if constexpr (MF == 0) {
+          if constexpr (n == 6) {
+            // at this order the fused kernel spills: A, then B^T added, then B (same results up
+            // to rounding order)
+            WB_REQUIRE(ep.mode == EPI_STORE && sin == nullptr, WB_EUNSUPPORTED,
+                       "fused Stokes operator: plain store only");
+            op_launch<n, 3, T, F_A | F_DIR, MF>(st, N, k, u, y, coef, nullptr, nullptr, nullptr, add,
+                                                work, ep);
+            op_launch<n, 3, T, F_BT | F_DIR, MF>(st, N, k, nullptr, y, nullptr, pin, nullptr, nullptr,
+                                                 true, work, ep);
+            return op_launch<n, 3, T, F_B | F_DIR, MF>(st, N, k, u, nullptr, nullptr, nullptr, pout,
+                                                       nullptr, false, work, ep);
+          } else {
+            return op_launch<n, 3, T, F_A | F_BT | F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout,
+                                                                    sin, add, work, ep);
+          }
+        }
         break;
       case F_B | F_DIR:
         return op_launch<n, 3, T, F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
@@ -1363,14 +1379,14 @@ template <int n, typename T>
 void op_dispatch_n(hipStream_t st, int flags, int NC, int N, int k, const T* u, T* y, const T* coef,
                    const T* pin, T* pout, const T* sin, bool add, void* work, const Epi<T>& ep) {
   if ((flags & (F_MF | F_MF3)) != 0) {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && n <= 5) {
       if ((flags & F_MF3) != 0)
         return op_dispatch_mf<n, T, 3>(st, flags & ~(F_MF | F_MF3), NC, N, k, u, y, coef, pin, pout,
                                        sin, add, work, ep);
       return op_dispatch_mf<n, T, 1>(st, flags & ~F_MF, NC, N, k, u, y, coef, pin, pout, sin, add,
                                      work, ep);
     }
-    throw Error{WB_EUNSUPPORTED, "BF16 contractions are built for FP32 data only"};
+    throw Error{WB_EUNSUPPORTED, "BF16 contractions are built for FP32 data and k <= 4 only"};
   }
   return op_dispatch_mf<n, T, 0>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
 }
@@ -2453,6 +2469,7 @@ size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size) {
     case 3: BX = Tile<3>::BX; BY = Tile<3>::BY; break;
     case 4: BX = Tile<4>::BX; BY = Tile<4>::BY; break;
     case 5: BX = Tile<5>::BX; BY = Tile<5>::BY; break;
+    case 6: BX = Tile<6>::BX; BY = Tile<6>::BY; break;
     default: break;
   }
   const BrickGeom G = brick_geom(N, k, BX, BY);
@@ -2467,6 +2484,7 @@ void launch_op_epi(hipStream_t st, int flags, int NC, int N, int k, const T* u, 
     case 3: return op_dispatch_n<3, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
     case 4: return op_dispatch_n<4, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
     case 5: return op_dispatch_n<5, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
+    case 6: return op_dispatch_n<6, T>(st, flags, NC, N, k, u, y, coef, pin, pout, sin, add, work, ep);
     default: throw Error{WB_EUNSUPPORTED, "order not built"};
   }
 }
@@ -2540,6 +2558,7 @@ template void launch_vcycle_tail<float>(hipStream_t, const TailArgs<float>&, con
     case 3: { constexpr int n = 3; __VA_ARGS__; } break;          \
     case 4: { constexpr int n = 4; __VA_ARGS__; } break;          \
     case 5: { constexpr int n = 5; __VA_ARGS__; } break;          \
+    case 6: { constexpr int n = 6; __VA_ARGS__; } break;          \
     default: throw Error{WB_EUNSUPPORTED, "order not built"};     \
   }
 

@@ -6,8 +6,8 @@
 
 namespace wb {
 
-constexpr int NMAX = 5;   // n = k+1 <= 5
-constexpr int NPMAX = 20; // modes for k = 4
+constexpr int NMAX = 6;   // n = k+1 <= 6
+constexpr int NPMAX = 35; // modes for k = 5
 
 // All 1D tables of one order k (n = k+1), double precision.
 struct Tables {

@@ -1034,7 +1034,9 @@ struct PhaseClock {
 
 Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes, const wb_opts& o,
                       hipStream_t st) {
-  WB_REQUIRE(m.k >= 2 && m.k <= 4, WB_EUNSUPPORTED, "Stokes solves need 2 <= k <= 4");
+  WB_REQUIRE(m.k >= 2 && m.k <= 5, WB_EUNSUPPORTED, "Stokes solves need 2 <= k <= 5");
+  WB_REQUIRE(m.k <= 4 || o.precond_prec == WB_FP64 || o.precond_prec == WB_FP32, WB_EUNSUPPORTED,
+             "the BF16 precision forms are built for k <= 4");
   WB_REQUIRE(o.cheb_degree >= 1 && o.restart >= 1 && o.max_iter >= 1 && o.rtol > 0, WB_EINVAL,
              "bad solver options");
   WB_REQUIRE(o.a_l >= 1.0 && o.a_r >= 1.0, WB_EINVAL, "boundary amplification must be >= 1");

@@ -15,7 +15,7 @@ int modes(int k, int* ma, int* mb, int* mc) { return rules::modes(k, ma, mb, mc)
 const Tables& tables(int k) {
   static constexpr Tables tab[NMAX] = {rules::build_tables(1), rules::build_tables(1),
                                        rules::build_tables(2), rules::build_tables(3),
-                                       rules::build_tables(4)};
+                                       rules::build_tables(4), rules::build_tables(5)};
   return tab[k];
 }
 

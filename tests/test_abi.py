@@ -54,7 +54,9 @@ def test_host_entry_points_without_gpu():
     h = ctypes.c_void_p()
     assert L.wb_mesh_create(0, 2, ctypes.byref(h)) == wb.WB_EINVAL
     assert b"N must be" in L.wb_last_error()
-    assert L.wb_mesh_create(8, 5, ctypes.byref(h)) == wb.WB_EUNSUPPORTED
+    assert L.wb_mesh_create(8, 6, ctypes.byref(h)) == wb.WB_EUNSUPPORTED
+    m = wb.Mesh(4, 5)
+    assert (m.n_nodes, m.n_p) == (21 ** 3, 35)
     assert L.wb_mesh_create(1025, 1, ctypes.byref(h)) == wb.WB_EINVAL
     assert L.wb_apply_A(None, None, None, None, None) == wb.WB_EINVAL
     assert L.wb_solve(None, None, None, None, None, None) == wb.WB_EINVAL

@@ -34,7 +34,9 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-CASES = [(9, 1), (8, 2), (7, 3), (5, 4)]
+CASES = [(9, 1), (8, 2), (7, 3), (5, 4), (3, 5)]
+# the BF16 matrix-core forms are built for k <= 4
+BF16_CASES = [c for c in CASES if c[1] <= 4]
 
 
 @pytest.mark.parametrize("N,k", CASES)
@@ -109,6 +111,17 @@ def test_apply_B_BT_stokes_match_assembled(N, k):
     assert _rel(host(yp), B @ ui) < 1e-12
 
 
+def test_bf16_forms_rejected_at_order_5():
+    wb = _wb()
+    m = wb.Mesh(3, 5)
+    nq = m.q_len
+    v = wb.Viscosity.values(m, dev(np.ones(nq)), dev(np.ones(m.n_nodes)))
+    u = torch.zeros(m.u_len, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(u)
+    with pytest.raises(Exception, match="k <= 4"):
+        wb.wb_apply_A_lowp(m, v, wb.WB_BF16, u, y)
+
+
 def test_apply_A_fp32_error_is_single_precision():
     wb = _wb()
     N, k = 8, 2
@@ -128,7 +141,7 @@ def test_apply_A_fp32_error_is_single_precision():
     assert 1e-9 < err < 1e-5
 
 
-@pytest.mark.parametrize("N,k", CASES)
+@pytest.mark.parametrize("N,k", BF16_CASES)
 @pytest.mark.parametrize("form", ["bf16x1", "bf16x3"])
 def test_apply_A_bf16_mfma_error(N, k, form):
     """BF16 forms: every 1D contraction runs on the BF16 matrix cores with FP32 accumulation.

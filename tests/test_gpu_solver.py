@@ -31,12 +31,13 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-# (workload, tolerance scale): c1 (two levels), an h-coarsened Q2 case, a Q3 and a Q4 case
+# c1 (two levels), an h-coarsened Q2 case, and Q3, Q4 and Q5 cases
 SETUPS = {
     "c1": WORKLOADS["c1"],
     "n8k2": custom("n8k2", 8, 2, n_sinkers=8, dr=1e6, a_r=2.0, seed=5),
     "n4k3": custom("n4k3", 4, 3, n_sinkers=4, dr=1e4, a_r=2.0, seed=6),
     "n4k4": custom("n4k4", 4, 4, n_sinkers=3, dr=1e4, a_l=2.0, a_r=1.0, seed=7),
+    "n4k5": custom("n4k5", 4, 5, n_sinkers=3, dr=1e4, a_r=2.0, seed=8),
 }
 
 _cache = {}
@@ -141,6 +142,29 @@ def test_fgmres_solution_matches_direct_solve(name):
     _, it_oracle, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
     assert rep6.rel_res <= 1e-6
     assert abs(rep6.iters - it_oracle) <= 2, (rep6.iters, it_oracle)
+
+
+def test_fgmres_order_5_matches_oracle():
+    # Q5 x P4-disc (the order sweep's top order): the FGMRES iteration count and solution at the
+    # paper's tolerance against the oracle's FGMRES with the oracle's preconditioner
+    wb = _wb()
+    w, st, P, m, v, s = _pair("n4k5")
+    om = st.mesh
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    assert _rel(host(f)[st.idx], st.F) < 1e-13
+    u = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    p = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    rep = s.solve(f, u, p)
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    _, it_oracle, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
+    assert rep.rel_res <= 1e-6
+    assert abs(rep.iters - it_oracle) <= 2, (rep.iters, it_oracle)
+    uh, ph = host(u), host(p)
+    assert np.all(uh[om.vel_boundary] == 0.0)
+    # the solution's residual under the oracle's own operator
+    res = b - st.stokes_matvec(np.concatenate([uh[st.idx], ph]))
+    assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(b)
 
 
 def test_mixed_precision_preconditioner_reaches_tolerance():
