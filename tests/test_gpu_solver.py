@@ -167,9 +167,10 @@ def test_fgmres_order_5_matches_oracle():
     assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(b)
 
 
-def test_mixed_precision_preconditioner_reaches_tolerance():
+@pytest.mark.parametrize("name", ["n8k2", "n4k5"])
+def test_mixed_precision_preconditioner_reaches_tolerance(name):
     wb = _wb()
-    w, st, P, m, v, s = _pair("n8k2")
+    w, st, P, m, v, s = _pair(name)
     om = st.mesh
     f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
     wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
