@@ -912,8 +912,10 @@ void cheb_K(Solver& s, Precond<T>& P, int side, const T* b, T* x, bool xzero) {
   if (pending) launch_axpby<T>(st, pl, T(1), d0, T(1), x);
 }
 
+// mean_out = false skips the final mean removal, for an output that only B^T reads (B^T with the
+// Dirichlet mask maps a constant pressure to zero).
 template <typename T>
-void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* b, T* x) {
+void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* b, T* x, bool mean_out) {
   hipStream_t st = s.st;
   const Mesh& m = s.m;
   cheb_K<T>(s, P, side, b, x, true);
@@ -928,7 +930,12 @@ void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* b, T* x) {
   vcycle<T>(s, H, 0, L0.b, L0.x);
   launch_modal_I<T>(st, m.N, m.k, L0.x, x, true);
   cheb_K<T>(s, P, side, b, x, false);
-  launch_remove_mean<T>(st, m.E, m.np, x, s.red_partial, s.red_out + 1);
+  if (mean_out) launch_remove_mean<T>(st, m.E, m.np, x, s.red_partial, s.red_out + 1);
+}
+
+template <typename T>
+void apply_vcycle_K(Solver& s, Precond<T>& P, int side, const T* b, T* x) {
+  apply_vcycle_K<T>(s, P, side, b, x, true);
 }
 
 template <typename T>
@@ -938,7 +945,7 @@ void apply_wbfbt(Solver& s, Precond<T>& P, const T* r, T* z) {
   const size_t pl = (size_t)m.E * m.np, vl = (size_t)3 * m.nn;
   WB_HIP(hipMemcpyAsync(P.pb, r, sizeof(T) * pl, hipMemcpyDeviceToDevice, st));
   launch_remove_mean<T>(st, m.E, m.np, P.pb, s.red_partial, s.red_out + 2);
-  apply_vcycle_K<T>(s, P, 1, P.pb, P.py);
+  apply_vcycle_K<T>(s, P, 1, P.pb, P.py, false);
   // middle product B C^-1 A D^-1 B^T
   launch_op<T>(st, F_BT | F_DIR | mf_flag<T>(s), 3, m.N, m.k, nullptr, P.v1, nullptr, P.py, nullptr, nullptr, false,
                s.opwork);
@@ -946,9 +953,10 @@ void apply_wbfbt(Solver& s, Precond<T>& P, const T* r, T* z) {
   launch_op<T>(st, F_A | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v1, P.v2, fine_mu(s, P), nullptr, nullptr, sr,
                false, s.opwork);
   const T* sl = weight_scaling<T>(s, P, 0, P.v2);
+  // B of a velocity that vanishes on the boundary has zero mean (the integral of its divergence
+  // is the boundary flux), so P.pm needs no mean removal
   launch_op<T>(st, F_B | F_DIR | mf_flag<T>(s), 3, m.N, m.k, P.v2, nullptr, nullptr, nullptr, P.pm, sl, false,
                nullptr);
-  launch_remove_mean<T>(st, m.E, m.np, P.pm, s.red_partial, s.red_out + 2);
   apply_vcycle_K<T>(s, P, 0, P.pm, z);
 }
 
