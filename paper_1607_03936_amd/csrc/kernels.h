@@ -197,6 +197,8 @@ void launch_cg_r(hipStream_t st, size_t n, const double* q, const double* dinv, 
                  const double* rz, const double* pq, double* partial, double* rz_new);
 void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const double* rz_new,
                  const double* rz_old);
+// y = x / sqrt(*d), d a device scalar (a squared norm); y = 0 when *d <= 0.
+void launch_scal_rnorm(hipStream_t st, size_t n, const double* d, const double* x, double* y);
 // x_i = 2 U(splitmix64(seed * 2^32 + i)) - 1, zero on boundary nodes of an [NC][M^3] vector
 // when M > 0 (the counter-based generator of the eigenvalue-estimate start vectors).
 void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int M, double* x);

@@ -2422,6 +2422,14 @@ k_cg_r(size_t n, const double* __restrict__ q, const double* __restrict__ dinv,
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
 }
+// y = x / sqrt(*d) (zero when *d <= 0): a normalization whose norm is still on the device.
+__global__ void k_scal_rnorm(size_t n, const double* __restrict__ d, const double* __restrict__ x,
+                             double* __restrict__ y) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = *d > 0.0 ? 1.0 / sqrt(*d) : 0.0;
+  y[i] = s * x[i];
+}
 __global__ void k_cg_p(size_t n, const double* __restrict__ z, double* __restrict__ p,
                        const double* __restrict__ rz_new, const double* __restrict__ rz_old) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2871,6 +2879,9 @@ void launch_cg_r(hipStream_t st, size_t n, const double* q, const double* dinv, 
 void launch_cg_p(hipStream_t st, size_t n, const double* z, double* p, const double* rz_new,
                  const double* rz_old) {
   hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n, 256)), dim3(256), 0, st, n, z, p, rz_new, rz_old);
+}
+void launch_scal_rnorm(hipStream_t st, size_t n, const double* d, const double* x, double* y) {
+  hipLaunchKernelGGL(k_scal_rnorm, dim3(grid_for(n, 256)), dim3(256), 0, st, n, d, x, y);
 }
 
 void launch_splitmix_vec(hipStream_t st, size_t n, unsigned long long seed, int M, double* x) {

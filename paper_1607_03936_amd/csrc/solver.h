@@ -120,6 +120,10 @@ struct Solver {
   // Krylov space
   size_t n_tot = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hbuf = nullptr, *mpartial = nullptr;
+  // per-iteration Arnoldi results copied to pinned host memory, two slots (one iteration may be
+  // enqueued ahead of the host's reading of the previous one), each with its completion event
+  double* hpin = nullptr;
+  hipEvent_t hev[2] = {};
   double *bvec = nullptr, *xvec = nullptr;
   double t_setup = 0.0;
   // preconditioner apply captured as a HIP graph (on cap_st, into the staging vectors gin/gout)

@@ -1015,6 +1015,9 @@ void apply_precond_any(Solver& s, const double* ru, const double* rp, double* zu
 // ------------------------------------------------------------------ setup
 Solver::~Solver() {
   if (pgraph) (void)hipGraphExecDestroy(pgraph);
+  for (int b = 0; b < 2; ++b)
+    if (hev[b]) (void)hipEventDestroy(hev[b]);
+  if (hpin) (void)hipHostFree(hpin);
   if (cap_st) (void)hipStreamDestroy(cap_st);
   for (int k = 0; k < AUX_STREAMS; ++k) {
     if (aux_ev[k]) (void)hipEventDestroy(aux_ev[k]);
@@ -1230,7 +1233,10 @@ Solver* solver_create(const Mesh& m, const double* mu_q, const double* mu_nodes,
   s.w = ar.alloc<double>(s.n_tot);
   s.bvec = ar.alloc<double>(s.n_tot);
   s.xvec = ar.alloc<double>(s.n_tot);
-  s.hbuf = ar.alloc<double>((size_t)3 * (R + 2));
+  // two slots of (h1, h2, |w|^2) = 2 (R + 2) + 1 values, then the R coefficients of the update
+  s.hbuf = ar.alloc<double>((size_t)5 * (R + 2));
+  WB_HIP(hipHostMalloc((void**)&s.hpin, sizeof(double) * 2 * (2 * (R + 2) + 1), hipHostMallocDefault));
+  for (int b = 0; b < 2; ++b) WB_HIP(hipEventCreateWithFlags(&s.hev[b], hipEventDisableTiming));
   s.mpartial = ar.alloc<double>((size_t)MDOT_BLOCKS * (R + 2));
   clk.mark("Krylov space");
   WB_HIP(hipStreamSynchronize(st));
@@ -1264,8 +1270,32 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
   if (bnorm > 0.0) {
     WB_HIP(hipMemcpyAsync(s.w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     double beta = bnorm;
-    std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), hh(2 * (R + 2) + 1);
+    std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1);
     std::vector<double> hist;
+    const size_t hs = (size_t)2 * (R + 2) + 1;  // one iteration's results: h1, h2, |w|^2
+    // Arnoldi step j: v_j (from the previous step's w and its norm, still on the device, unless
+    // j = 0), z_j = P v_j, w = K z_j, two classical Gram-Schmidt passes and |w|^2, then the
+    // results go to the pinned slot j % 2 and its event is recorded.
+    auto enqueue = [&](int j) {
+      double* hb = s.hbuf + (size_t)(j & 1) * hs;
+      double* vj = s.V + (size_t)j * n;
+      double* zj = s.Z + (size_t)j * n;
+      if (j > 0) launch_scal_rnorm(st, n, s.hbuf + (size_t)((j - 1) & 1) * hs + 2 * (R + 2), s.w, vj);
+      precond(vj, zj);
+      matvec(zj, s.w);
+      launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, hb);
+      launch_gemv_sub(st, n, j + 1, s.V, n, hb, s.w);
+      launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, hb + (R + 2));
+      launch_gemv_sub(st, n, j + 1, s.V, n, hb + (R + 2), s.w);
+      launch_dot<double>(st, n, s.w, s.w, s.red_partial, hb + 2 * (R + 2));
+      WB_HIP(hipMemcpyAsync(s.hpin + (size_t)(j & 1) * hs, hb, sizeof(double) * hs,
+                            hipMemcpyDeviceToHost, st));
+      WB_HIP(hipEventRecord(s.hev[j & 1], st));
+    };
+    // Step j + 1 is enqueued before step j's results are read (hiding the host round trip) only
+    // while the residual estimate is far above the target, so that step j cannot plausibly
+    // converge; a step enqueued in vain would delay the solution update by one iteration.
+    constexpr double kAhead = 50.0;
     bool done = false;
     while (!done) {
       std::fill(H.begin(), H.end(), 0.0);
@@ -1273,26 +1303,19 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
       g[0] = beta;
       launch_scal<double>(st, n, 1.0 / beta, s.w, s.V);
       int jdone = 0;
+      enqueue(0);
       for (int j = 0; j < R; ++j) {
-        double* vj = s.V + (size_t)j * n;
-        double* zj = s.Z + (size_t)j * n;
-        precond(vj, zj);
-        matvec(zj, s.w);
-        double* h1 = s.hbuf;
-        double* h2 = s.hbuf + (R + 2);
-        launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, h1);
-        launch_gemv_sub(st, n, j + 1, s.V, n, h1, s.w);
-        launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, h2);
-        launch_gemv_sub(st, n, j + 1, s.V, n, h2, s.w);
-        launch_dot<double>(st, n, s.w, s.w, s.red_partial, s.hbuf + 2 * (R + 2));
-        WB_HIP(hipMemcpyAsync(hh.data(), s.hbuf, sizeof(double) * (2 * (R + 2) + 1),
-                              hipMemcpyDeviceToHost, st));
-        WB_HIP(hipStreamSynchronize(st));
+        bool ahead = false;
+        if (j + 1 < R && it + 1 < max_iter && std::fabs(g[j]) > kAhead * rtol * bnorm) {
+          enqueue(j + 1);
+          ahead = true;
+        }
+        WB_HIP(hipEventSynchronize(s.hev[j & 1]));
+        const double* hh = s.hpin + (size_t)(j & 1) * hs;
         const double nrm = std::sqrt(hh[2 * (R + 2)]);
         if (!std::isfinite(nrm)) throw Error{WB_ENAN, "NaN/Inf in the Krylov vector"};
         for (int i = 0; i <= j; ++i) H[(size_t)i * R + j] = hh[i] + hh[(R + 2) + i];
         H[(size_t)(j + 1) * R + j] = nrm;
-        if (nrm > 0.0) launch_scal<double>(st, n, 1.0 / nrm, s.w, s.V + (size_t)(j + 1) * n);
         for (int i = 0; i < j; ++i) {
           const double a = H[(size_t)i * R + j], bb = H[(size_t)(i + 1) * R + j];
           H[(size_t)i * R + j] = cs[i] * a + sn[i] * bb;
@@ -1323,7 +1346,10 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
             s.pgraph = nullptr;
           }
         }
+        // a step enqueued ahead of a stop runs to completion unused; the update below reads
+        // only Z_0 .. Z_j and its own coefficient slot
         if (std::fabs(g[j + 1]) <= rtol * bnorm || it >= max_iter || nrm == 0.0) break;
+        if (!ahead && j + 1 < R) enqueue(j + 1);
       }
       std::vector<double> y(jdone);
       for (int i = jdone - 1; i >= 0; --i) {
@@ -1331,8 +1357,9 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
         for (int c = i + 1; c < jdone; ++c) t -= H[(size_t)i * R + c] * y[c];
         y[i] = t / H[(size_t)i * R + i];
       }
-      WB_HIP(hipMemcpyAsync(s.hbuf, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, st));
-      launch_gemv_add(st, n, jdone, s.Z, n, s.hbuf, s.xvec);
+      double* yd = s.hbuf + 2 * hs;
+      WB_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, st));
+      launch_gemv_add(st, n, jdone, s.Z, n, yd, s.xvec);
       // true residual
       matvec(s.xvec, s.w);
       launch_axpby<double>(st, n, 1.0, b, -1.0, s.w);
