@@ -6,7 +6,9 @@
 // basis, multiplied by the pointwise coefficient and pulled back by the
 // transposed contractions (Sec. 1.2 discretization, eq. 2).  Thread layout:
 // n^2 threads per element, each holding a z-column in registers; x and y
-// contractions exchange through LDS.
+// contractions exchange through LDS.  The divergence and the gradient alone
+// use the precomputed tensor-product element matrix of the uniform mesh
+// (k_div_line, k_grad_line).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -824,7 +826,9 @@ struct WinPad {
   static constexpr int WXS = WX, WPS = WX * WY;
 };
 
-// Divergence only (no scatter): element-parallel, the pressure modes go through the epilogue.
+// Divergence only (no scatter) with the sum-factorized element machinery, element-parallel; the
+// pressure modes go through the epilogue.  Used by the BF16 forms (their contractions on the
+// matrix cores); the other forms use k_div_line.
 template <int n, typename T, int F, int MF, int EP>
 __global__ void __launch_bounds__(256)
 k_op_gather(const int N, const int k, const int M, const int E, const int nn, const T hh,
