@@ -732,6 +732,15 @@ struct BrickGeom {
   size_t per_comp;       // face-array elements per component
 };
 
+// The two-pass form (k_op_elem + k_node_sum) is used while the element contributions take at
+// most this many bytes in FP64; larger problems use the brick scatter (no element buffer in HBM).
+// The choice does not depend on the data type, so a workspace sized for FP64 serves FP32 too.
+constexpr size_t TWO_PASS_MAX_BYTES = 128u << 20;
+inline bool two_pass(int NC, int N, int k) {
+  const size_t n3 = (size_t)(k + 1) * (k + 1) * (k + 1);
+  return sizeof(double) * NC * (size_t)N * N * N * n3 <= TWO_PASS_MAX_BYTES;
+}
+
 inline BrickGeom brick_geom(int N, int k, int BX, int BY) {
   BrickGeom g;
   g.N = N;
@@ -854,6 +863,91 @@ k_op_gather(const int N, const int k, const int M, const int E, const int nn, co
   element_op<n, 3, T, F, MF>(valid, e, k, hh, in, nullptr,
                              [&](size_t j, T v) { emit<EP>(ep, j, v, pout, add); }, s0,
                              s0 + (SLOTS + 1) * SL, r, [](int, int, int, int, T) {});
+}
+
+// Two-pass form of the node-scattering operators (A, Poisson) for problems small enough that the
+// element contributions fit in a modest buffer: every element runs in parallel (no brick march,
+// no LDS window) and stores its NC n^3 contributions, [E][NC][n^3]; then each node sums those of
+// the at most eight elements containing it, in a fixed order, and goes through the epilogue.
+template <int n, int NC, typename T, int F, int MF, int EP>
+__global__ void __launch_bounds__(256)
+k_op_elem(const int N, const int k, const int M, const int E, const int nn, const T hh,
+          const T* __restrict__ u, const T* __restrict__ coef, const T* __restrict__ sin_,
+          T* __restrict__ buf, const Epi<T> ep) {
+  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW, SL = Lds<n, sizeof(T)>::SL;
+  constexpr int N3 = n * n * n;
+  __shared__ T sm[2 * (SLOTS + 1) * SL];
+  int slot, r;
+  bool lane_ok;
+  WaveMap<n>::map(threadIdx.x, slot, r, lane_ok);
+  const int e = blockIdx.x * SLOTS + slot;
+  const bool valid = lane_ok && e < E;
+  int ex = 0, ey = 0, ez = 0;
+  if (valid) {
+    ex = e % N;
+    const int q = e / N;
+    ey = q % N;
+    ez = q / N;
+  }
+  T* s0 = sm + (lane_ok ? slot : SLOTS) * SL;
+  ElemIn<n, NC, T> in;
+  if constexpr (EP == EPI_CHEB_ZERO)
+    element_load<n, NC, T, F, true>(valid, e, ex, ey, ez, k, M, nn, ep.b, coef, sin_, r, in, ep.dinv,
+                                    ep.gamma);
+  else
+    element_load<n, NC, T, F>(valid, e, ex, ey, ez, k, M, nn, u, coef, sin_, r, in);
+  T* be = buf + (size_t)(valid ? e : 0) * NC * N3;
+  element_op<n, NC, T, F, MF>(valid, e, k, hh, in, nullptr, [](size_t, T) {}, s0,
+                              s0 + (SLOTS + 1) * SL, r, [&](int c, int x, int yy, int z, T v) {
+                                if (valid) be[c * N3 + x + n * (yy + n * z)] = v;
+                              });
+}
+
+template <int n, int NC, typename T, bool DIR, int EP>
+__global__ void __launch_bounds__(256)
+k_node_sum(const int N, const int M, const int nn, const T* __restrict__ buf, T* __restrict__ y,
+           const int add, const Epi<T> ep) {
+  constexpr int k = n - 1, N3 = n * n * n;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nn) return;
+  const int gc[3] = {g % M, (g / M) % M, g / (M * M)};
+  T val[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) val[c] = T(0);
+  const bool bnd = DIR && (gc[0] == 0 || gc[0] == M - 1 || gc[1] == 0 || gc[1] == M - 1 ||
+                           gc[2] == 0 || gc[2] == M - 1);
+  if (!bnd) {
+    // per direction: element of the first candidate and its local index, and whether the second
+    // candidate (the next element, local index 0) exists
+    int e0[3], l0[3];
+    bool has0[3], has1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int rr = gc[d] % k, q = gc[d] / k;
+      const bool vert = rr == 0;
+      has0[d] = !vert || q > 0;
+      has1[d] = vert && q < N;
+      e0[d] = vert ? q - 1 : q;
+      l0[d] = vert ? k : rr;
+    }
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+      for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+          if (!((sx ? has1[0] : has0[0]) && (sy ? has1[1] : has0[1]) && (sz ? has1[2] : has0[2])))
+            continue;
+          const int ex = sx ? e0[0] + 1 : e0[0], ey = sy ? e0[1] + 1 : e0[1], ez = sz ? e0[2] + 1 : e0[2];
+          const int lx = sx ? 0 : l0[0], ly = sy ? 0 : l0[1], lz = sz ? 0 : l0[2];
+          const T* be = buf + ((size_t)ex + (size_t)N * (ey + (size_t)N * ez)) * NC * N3 +
+                        lx + n * (ly + n * lz);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) val[c] += be[c * N3];
+        }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) emit<EP>(ep, (size_t)c * nn + g, val[c], y, add);
 }
 
 // Scatter operator: y = op(u) (or y += op(u)), F_B output as well when requested.
@@ -1289,6 +1383,22 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
     hipLaunchKernelGGL((k_grad_line<n, T>), dim3(grid_for((size_t)N * M * M, 256)), dim3(256), 0, st,
                        N, M, nn, hh, pin, y, (int)add);
   } else {
+    // plain-store vector applies keep the brick: its face pass is cheap without an epilogue
+    if constexpr ((F & (F_BT | F_B)) == 0 && (NC == 1 || EP != EPI_STORE)) {
+      if (two_pass(NC, N, k)) {
+        constexpr int SLOTS = 4 * WaveMap<n>::EPW;
+        T* buf = static_cast<T*>(work);
+        {
+          ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
+          hipLaunchKernelGGL((k_op_elem<n, NC, T, F, MF, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0,
+                             st, N, k, M, E, nn, hh, u, coef, sin, buf, ep);
+        }
+        ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), "-faces"));
+        hipLaunchKernelGGL((k_node_sum<n, NC, T, (F & F_DIR) != 0, EP>), dim3(grid_for(nn, 256)),
+                           dim3(256), 0, st, N, M, nn, buf, y, (int)add, ep);
+        return;
+      }
+    }
     constexpr int BX = Tile<n>::BX, BY = Tile<n>::BY;
     const BrickGeom G = brick_geom(N, k, BX, BY);
     const BrickDev D = brick_dev(G);
@@ -2475,6 +2585,9 @@ __global__ void k_sub_mean(size_t n, double* __restrict__ x, const double* __res
 
 // ================================================================== launchers
 size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size) {
+  const size_t elem_buf = two_pass(NC, N, k)
+                              ? elem_size * NC * (size_t)N * N * N * (k + 1) * (k + 1) * (k + 1)
+                              : 0;
   int BX = 8, BY = 8;
   switch (k + 1) {
     case 2: BX = Tile<2>::BX; BY = Tile<2>::BY; break;
@@ -2485,7 +2598,7 @@ size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size) {
     default: break;
   }
   const BrickGeom G = brick_geom(N, k, BX, BY);
-  return elem_size * NC * std::max<size_t>(G.per_comp, 1);
+  return std::max(elem_buf, elem_size * NC * std::max<size_t>(G.per_comp, 1));
 }
 
 template <typename T>
