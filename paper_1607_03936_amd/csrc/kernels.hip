@@ -867,8 +867,10 @@ k_op_gather(const int N, const int k, const int M, const int E, const int nn, co
 
 // Two-pass form of the node-scattering operators (A, Poisson) for problems small enough that the
 // element contributions fit in a modest buffer: every element runs in parallel (no brick march,
-// no LDS window) and stores its NC n^3 contributions, [E][NC][n^3]; then each node sums those of
+// no LDS window) and stores its NC n^3 contributions; then each node sums those of
 // the at most eight elements containing it, in a fixed order, and goes through the epilogue.
+// The buffer is [NC][n^3][E] (element index fastest): the node sums of a wavefront, which walk
+// along x through consecutive elements, then read contiguous runs.
 template <int n, int NC, typename T, int F, int MF, int EP>
 __global__ void __launch_bounds__(256)
 k_op_elem(const int N, const int k, const int M, const int E, const int nn, const T hh,
@@ -896,10 +898,10 @@ k_op_elem(const int N, const int k, const int M, const int E, const int nn, cons
                                     ep.gamma);
   else
     element_load<n, NC, T, F>(valid, e, ex, ey, ez, k, M, nn, u, coef, sin_, r, in);
-  T* be = buf + (size_t)(valid ? e : 0) * NC * N3;
   element_op<n, NC, T, F, MF>(valid, e, k, hh, in, nullptr, [](size_t, T) {}, s0,
                               s0 + (SLOTS + 1) * SL, r, [&](int c, int x, int yy, int z, T v) {
-                                if (valid) be[c * N3 + x + n * (yy + n * z)] = v;
+                                if (valid)
+                                  buf[(size_t)(c * N3 + x + n * (yy + n * z)) * E + e] = v;
                               });
 }
 
@@ -940,10 +942,11 @@ k_node_sum(const int N, const int M, const int nn, const T* __restrict__ buf, T*
             continue;
           const int ex = sx ? e0[0] + 1 : e0[0], ey = sy ? e0[1] + 1 : e0[1], ez = sz ? e0[2] + 1 : e0[2];
           const int lx = sx ? 0 : l0[0], ly = sy ? 0 : l0[1], lz = sz ? 0 : l0[2];
-          const T* be = buf + ((size_t)ex + (size_t)N * (ey + (size_t)N * ez)) * NC * N3 +
-                        lx + n * (ly + n * lz);
+          const size_t E = (size_t)N * N * N;
+          const T* be = buf + (size_t)(lx + n * (ly + n * lz)) * E + (size_t)ex +
+                        (size_t)N * (ey + (size_t)N * ez);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) val[c] += be[c * N3];
+          for (int c = 0; c < NC; ++c) val[c] += be[(size_t)c * N3 * E];
         }
   }
 #pragma unroll
