@@ -1386,8 +1386,7 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
     hipLaunchKernelGGL((k_grad_line<n, T>), dim3(grid_for((size_t)N * M * M, 256)), dim3(256), 0, st,
                        N, M, nn, hh, pin, y, (int)add);
   } else {
-    // plain-store vector applies keep the brick: its face pass is cheap without an epilogue
-    if constexpr ((F & (F_BT | F_B)) == 0 && (NC == 1 || EP != EPI_STORE)) {
+    if constexpr ((F & (F_BT | F_B)) == 0) {
       if (two_pass(NC, N, k)) {
         constexpr int SLOTS = 4 * WaveMap<n>::EPW;
         T* buf = static_cast<T*>(work);

@@ -6,9 +6,10 @@ python -m paper_1607_03936_amd.trafficsummary <out.json> <workload> <fetch.csv> 
 Each workload names the counter_collection.csv of its FETCH_SIZE run and of its WRITE_SIZE run
 (opbench.py <workload> <reps> copy).  The copy leg moves a known number of bytes (the velocity
 vector, read once and written once), so bytes / counter gives each counter's unit; the factors of
-all workloads are averaged.  Prints a text summary and writes the per-launch bytes of the A
-apply kernel class to <out.json>, keyed like bench.py's kernel keys, with the source hash of
-the kernels the counters were taken on.
+all workloads are averaged.  An A apply is two kernels (the brick scatter and its face sums, or
+the element pass and its node sums); prints a text summary of both and writes the per-apply
+bytes of the pair to <out.json>, keyed like bench.py's kernel keys, with the source hash of the
+kernels the counters were taken on.
 """
 from __future__ import annotations
 
@@ -23,8 +24,8 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-A_KERNEL = re.compile(r"k_op_brick<(\d), 3, double, 9, 0, 0>")
-FACE_KERNEL = re.compile(r"k_face_sum<(\d), 3, double, true, 0>")
+A_KERNEL = re.compile(r"k_op_(brick|elem)<(\d), 3, double, 9, 0, 0>")
+FACE_KERNEL = re.compile(r"k_(face|node)_sum<(\d), 3, double, true, 0>")
 
 
 def source_hash() -> str:
@@ -38,6 +39,7 @@ def source_hash() -> str:
 def read(path):
     """{kernel class: [counter value per dispatch]}, plus the copy dispatches as (grid, value)."""
     per = defaultdict(list)
+    names = {}
     copies = []
     with open(path, newline="") as fh:
         for row in csv.DictReader(fh):
@@ -46,8 +48,11 @@ def read(path):
                 copies.append((int(row["Grid_Size"]), val))
             elif A_KERNEL.search(name):
                 per["A"].append(val)
+                names["A"] = A_KERNEL.search(name).group(1)
             elif FACE_KERNEL.search(name):
                 per["face"].append(val)
+                names["face"] = FACE_KERNEL.search(name).group(1)
+    per["names"] = names
     return per, copies
 
 
@@ -85,21 +90,29 @@ def main(argv):
     kernels = {}
     for name, w, u_dof, nq, fper, wper in rows:
         algo = 8.0 * (2 * u_dof + nq)
+        tot = {"fetch_kib": 0.0, "write_kib": 0.0, "bytes": 0.0}
+        form = fper["names"].get("A", "brick")
         for cls in ("A", "face"):
             if not fper.get(cls) or not wper.get(cls):
                 continue
             fk = sum(fper[cls]) / len(fper[cls])
             wk = sum(wper[cls]) / len(wper[cls])
             rd, wr = fk * kf * 1024, wk * kw * 1024
-            label = f"k_op_brick<{w.k + 1},3,double,9,0,0>" if cls == "A" else "k_face_sum (same applies)"
-            ratio = f"{(rd + wr) / algo:6.2f}" if cls == "A" else ""
-            am = f"{algo / 1e6:9.2f}" if cls == "A" else ""
-            print(f"{name:<10} {label:<30} {len(fper[cls]):>5} {fk:>10.0f} {wk:>10.0f} {rd / 1e6:>9.2f} "
-                  f"{wr / 1e6:>9.2f} {(rd + wr) / 1e6:>10.2f} {am:>9} {ratio:>6}")
+            tot["fetch_kib"] += fk
+            tot["write_kib"] += wk
+            tot["bytes"] += rd + wr
             if cls == "A":
-                key = f"op nc=3 k={w.k} N={w.N} flags=A+dir f64"
-                kernels[key] = {"fetch_kib": round(fk), "write_kib": round(wk),
-                                "bytes_per_launch": round(rd + wr)}
+                label = f"k_op_{form}<{w.k + 1},3,double,9,0,0>"
+            else:
+                label = f"k_{fper['names'].get('face', 'face')}_sum (same applies)"
+            print(f"{name:<10} {label:<30} {len(fper[cls]):>5} {fk:>10.0f} {wk:>10.0f} {rd / 1e6:>9.2f} "
+                  f"{wr / 1e6:>9.2f} {(rd + wr) / 1e6:>10.2f} {'':>9} {'':>6}")
+        print(f"{name:<10} {'whole apply (both kernels)':<30} {'':>5} {tot['fetch_kib']:>10.0f} "
+              f"{tot['write_kib']:>10.0f} {'':>9} {'':>9} {tot['bytes'] / 1e6:>10.2f} {algo / 1e6:>9.2f} "
+              f"{tot['bytes'] / algo:>6.2f}")
+        key = f"op nc=3 k={w.k} N={w.N} flags=A+dir f64"
+        kernels[key] = {"fetch_kib": round(tot["fetch_kib"]), "write_kib": round(tot["write_kib"]),
+                        "bytes_per_launch": round(tot["bytes"])}
     rec = {"source_hash": source_hash(),
            "calibration": {"FETCH_SIZE": round(kf, 3), "WRITE_SIZE": round(kw, 3),
                            "reference": "device copy of the velocity vector (opbench.py copy leg)"},
