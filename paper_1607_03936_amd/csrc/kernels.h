@@ -23,9 +23,12 @@ enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8, F_MF = 16, F_MF3 = 32 };
 //   y    = op(u)  (or y += op(u) when add)  [NC][nn]; every node is written, no zeroing needed
 //   pout = B u   (written)                   [E][np]
 //   sin: optional per-node input scaling.
-// Operators that scatter to nodes (A, the fused Stokes operator) run in two kernels: blocks own
-// bricks of elements and accumulate in LDS; values on internal brick faces pass through `work`
-// (at least op_workspace_bytes(NC, N, k, sizeof(T)) bytes) and are summed by a second kernel.
+// Operators that scatter to nodes (A, the fused Stokes operator) run in two kernels, with `work`
+// at least op_workspace_bytes(NC, N, k, sizeof(double)) bytes (valid for FP32 data as well):
+//  - A alone while its element contributions fit in 128 MB (FP64): all elements in parallel into
+//    an element buffer in `work`, then per-node sums of the at most eight contributions;
+//  - otherwise, and for the fused Stokes operator: blocks own bricks of elements and accumulate
+//    in LDS; values on internal brick faces pass through `work` and are summed by a second kernel.
 // B alone and B^T alone (outside the BF16 forms) use the uniform mesh's tensor-product element
 // matrix instead: B one element x-line per lane, B^T one node line segment per thread, one
 // kernel each and no workspace.
