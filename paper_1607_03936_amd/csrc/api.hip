@@ -465,6 +465,8 @@ wb_status wb_solver_levels(wb_solver* sh, int which, int* nlevels, int* Ns, int*
 
 void wb_profile_enable(int on) { profile_enable(on != 0); }
 
+double wb_set_two_pass_limit(double mb) { return set_two_pass_limit(mb); }
+
 long long wb_profile_summary(char* buf, long long len, int reset) {
   std::string s = profile_summary(reset != 0);
   if (buf && len > 0) {

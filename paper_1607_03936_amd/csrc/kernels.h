@@ -33,6 +33,9 @@ enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8, F_MF = 16, F_MF3 = 32 };
 // matrix instead: B one element x-line per lane, B^T one node line segment per thread, one
 // kernel each and no workspace.
 size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size);
+// Process-wide size limit (MB of FP64 element contributions, clamped to [0, 128]) below which A
+// applies use the two-pass form; returns the previous limit.
+double set_two_pass_limit(double mb);
 
 // What an operator kernel does with each finished output value v at index j:
 //   EPI_STORE       y_j = v (or y_j += v when add)

@@ -10,6 +10,7 @@
 // use the precomputed tensor-product element matrix of the uniform mesh
 // (k_div_line, k_grad_line).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -733,12 +734,17 @@ struct BrickGeom {
 };
 
 // The two-pass form (k_op_elem + k_node_sum) is used while the element contributions take at
-// most this many bytes in FP64; larger problems use the brick scatter (no element buffer in HBM).
-// The choice does not depend on the data type, so a workspace sized for FP64 serves FP32 too.
+// most two_pass_limit bytes in FP64 (at most TWO_PASS_MAX_BYTES, the default); larger problems use
+// the brick scatter (no element buffer in HBM).  The choice does not depend on the data type, so
+// a workspace sized for FP64 serves FP32 too, and workspaces are sized for both forms up to the
+// cap, so the limit may change while solvers exist.
 constexpr size_t TWO_PASS_MAX_BYTES = 128u << 20;
+std::atomic<size_t> two_pass_limit{TWO_PASS_MAX_BYTES};
+inline size_t elem_buf_bytes(int NC, int N, int k) {
+  return sizeof(double) * NC * (size_t)N * N * N * (size_t)(k + 1) * (k + 1) * (k + 1);
+}
 inline bool two_pass(int NC, int N, int k) {
-  const size_t n3 = (size_t)(k + 1) * (k + 1) * (k + 1);
-  return sizeof(double) * NC * (size_t)N * N * N * n3 <= TWO_PASS_MAX_BYTES;
+  return elem_buf_bytes(NC, N, k) <= two_pass_limit.load(std::memory_order_relaxed);
 }
 
 inline BrickGeom brick_geom(int N, int k, int BX, int BY) {
@@ -2586,9 +2592,16 @@ __global__ void k_sub_mean(size_t n, double* __restrict__ x, const double* __res
 }  // namespace
 
 // ================================================================== launchers
+double set_two_pass_limit(double mb) {
+  const double prev = (double)two_pass_limit.load() / 1e6;
+  const double b = std::min(std::max(mb, 0.0) * 1e6, (double)TWO_PASS_MAX_BYTES);
+  two_pass_limit.store((size_t)b);
+  return prev;
+}
+
 size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size) {
-  const size_t elem_buf = two_pass(NC, N, k)
-                              ? elem_size * NC * (size_t)N * N * N * (k + 1) * (k + 1) * (k + 1)
+  const size_t elem_buf = elem_buf_bytes(NC, N, k) <= TWO_PASS_MAX_BYTES
+                              ? elem_buf_bytes(NC, N, k) / sizeof(double) * elem_size
                               : 0;
   int BX = 8, BY = 8;
   switch (k + 1) {

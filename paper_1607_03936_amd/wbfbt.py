@@ -106,6 +106,7 @@ SIGNATURES = {
     "wb_net_feature": (I, [I, VP, VP, VP]),
     "wb_mem_trim": (None, []),
     "wb_profile_enable": (None, [I]),
+    "wb_set_two_pass_limit": (D, [D]),
     "wb_profile_summary": (LL, [ctypes.c_char_p, LL, I]),
 }
 
@@ -237,6 +238,10 @@ def wb_apply_A_add(mesh, visc, u, y, stream=None):
 
 def wb_profile_enable(on: bool):
     lib().wb_profile_enable(1 if on else 0)
+
+
+def wb_set_two_pass_limit(mb: float) -> float:
+    return lib().wb_set_two_pass_limit(float(mb))
 
 
 def wb_profile_summary(reset: bool = True):

@@ -239,3 +239,29 @@ def test_apply_B_BT_full_size_sampled_rows(name):
             want[t] += Be[:, c * n3 + li] @ p[e * npm:(e + 1) * npm]
     assert np.abs(got_u[dofs] - want).max() <= 1e-12 * np.abs(want).max()
     assert np.all(got_u[om.vel_boundary] == 0.0)
+
+
+@pytest.mark.parametrize("N,k", [(8, 2), (5, 4)])
+def test_apply_A_brick_and_two_pass_forms_match_assembled(N, k):
+    # the two forms of the A apply (brick scatter with face sums; element pass with node sums),
+    # each against the assembled oracle
+    wb = _wb()
+    om = fem.Mesh(N, k)
+    rng = np.random.default_rng(11)
+    mu_q = np.exp(rng.uniform(-3, 3, (om.E, om.n ** 3)))
+    m = wb.Mesh(N, k)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(np.ones(om.n_nodes)))
+    u = random_vector(12, om.u_dof)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0.0
+    want = fem.assemble_A(om, mu_q) @ ui
+    want[om.vel_boundary] = 0.0
+    prev = wb.wb_set_two_pass_limit(128.0)
+    try:
+        for limit in (0.0, 128.0):
+            wb.wb_set_two_pass_limit(limit)
+            y = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+            wb.wb_apply_A(m, v, dev(u), y)
+            assert _rel(host(y), want) < 1e-12, limit
+    finally:
+        wb.wb_set_two_pass_limit(prev)

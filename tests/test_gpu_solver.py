@@ -167,6 +167,39 @@ def test_fgmres_order_5_matches_oracle():
     assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(b)
 
 
+def test_brick_form_preconditioner_matches_oracle():
+    # every A and Poisson apply in the brick form (the form large problems use): K_w, the
+    # V-cycles and the preconditioner against the oracle, and the FGMRES iteration count
+    wb = _wb()
+    w, st, P, m, v, _ = _pair("n8k2")
+    om = st.mesh
+    prev = wb.wb_set_two_pass_limit(0.0)
+    try:
+        s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r)
+        r = st.remove_mean(random_vector(31, om.p_dof))
+        out = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+        s.vcycle_K(0, dev(r), out)
+        assert _rel(host(out), P.k_vcycle("l", r)) < 1e-9
+        ru = random_vector(32, om.u_dof)
+        ru[om.vel_boundary] = 0.0
+        zu = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+        zp = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+        s.precond(dev(ru), dev(r), zu, zp)
+        ref = P.apply(np.concatenate([ru[st.idx], r]))
+        assert _rel(host(zu), st.embed_u(ref[:st.nu])) < 1e-9
+        assert _rel(host(zp), ref[st.nu:]) < 1e-9
+        f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+        wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+        u = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+        rep = s.solve(f, u, zp)
+        b = np.concatenate([st.F, np.zeros(st.np_)])
+        _, it_oracle, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
+        assert rep.rel_res <= 1e-6
+        assert abs(rep.iters - it_oracle) <= 2, (rep.iters, it_oracle)
+    finally:
+        wb.wb_set_two_pass_limit(prev)
+
+
 @pytest.mark.parametrize("name", ["n8k2", "n4k5"])
 def test_mixed_precision_preconditioner_reaches_tolerance(name):
     wb = _wb()
