@@ -91,7 +91,7 @@ typedef struct {
                              +1: eq. (3) as printed                              */
   double assemble_mb;     /* Q1 multigrid levels whose assembled 27-point stencil
                              takes at most this many MB (FP64) are applied as
-                             stencils instead of element kernels (100); the coarsest
+                             stencils instead of element kernels (32); the coarsest
                              level is always assembled; 0: element kernels only   */
   int schur_approx;       /* Schur block of the preconditioner: 0 (default) w-BFBT
                              (eq. 8); 1 the inverse viscosity-weighted pressure

@@ -96,7 +96,7 @@ void wb_opts_default(wb_opts* o) {
   o->verbose = 0;
   o->use_graph = 1;
   o->schur_sign = -1;
-  o->assemble_mb = 100.0;
+  o->assemble_mb = 32.0;
   o->schur_approx = 0;
   o->weights = 0;
 }

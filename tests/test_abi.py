@@ -78,6 +78,6 @@ def test_opts_struct_matches_header():
     assert [(n, ct[t]) for n, t in names] == list(wb.wb_opts._fields_)
     o = wb.opts()
     assert (o.use_graph, o.schur_sign, o.schur_approx, o.weights) == (1, -1, 0, 0)
-    assert o.assemble_mb == 100.0
+    assert o.assemble_mb == 32.0
     with pytest.raises(TypeError):
         wb.opts(no_such_option=1)
