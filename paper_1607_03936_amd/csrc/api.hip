@@ -467,6 +467,8 @@ void wb_profile_enable(int on) { profile_enable(on != 0); }
 
 double wb_set_two_pass_limit(double mb) { return set_two_pass_limit(mb); }
 
+int wb_set_matrix_core_ops(int on) { return set_matrix_core_ops(on); }
+
 long long wb_profile_summary(char* buf, long long len, int reset) {
   std::string s = profile_summary(reset != 0);
   if (buf && len > 0) {

@@ -36,6 +36,9 @@ size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size);
 // Process-wide size limit (MB of FP64 element contributions, clamped to [0, 128]) below which A
 // applies use the two-pass form; returns the previous limit.
 double set_two_pass_limit(double mb);
+// FP64 order-3 applies of A and the Poisson operator above the two-pass size: on the FP64 matrix
+// cores (on != 0, the default) or with line contractions staged in LDS; returns the previous setting.
+int set_matrix_core_ops(int on);
 
 // What an operator kernel does with each finished output value v at index j:
 //   EPI_STORE       y_j = v (or y_j += v when add)

@@ -740,6 +740,9 @@ struct BrickGeom {
 // cap, so the limit may change while solvers exist.
 constexpr size_t TWO_PASS_MAX_BYTES = 128u << 20;
 std::atomic<size_t> two_pass_limit{TWO_PASS_MAX_BYTES};
+// FP64 order-3 brick applies of A and the Poisson operator on the matrix cores (k_op_mfma) or with
+// line contractions in LDS (k_op_brick).
+std::atomic<int> matrix_core_ops{1};
 inline size_t elem_buf_bytes(int NC, int N, int k) {
   return sizeof(double) * NC * (size_t)N * N * N * (size_t)(k + 1) * (k + 1) * (k + 1);
 }
@@ -1050,6 +1053,253 @@ k_op_brick(const BrickDev G, const T hh, const T* __restrict__ u,
     for (int c = 0; c < NC; ++c) val[c] = win[(c * (k + 1)) * WPS + wy * WXS + wx];
     store_node<n, NC, T, (F & F_DIR) != 0, EP>(G, gx, gy, Z1, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
   }
+}
+
+// ------------------------------------------------------------ matrix-core FP64 operator, order 3
+// The node-scattering operators (A, Poisson) at order 3 with FP64 data, brick geometry and face
+// array as k_op_brick, but with the 1D contractions in x and y on the FP64 matrix cores.
+// v_mfma_f64_4x4x4_4b computes four independent 4x4x4 products D = A B + C, one double of A, B
+// and D per lane.  Lane layout (measured on gfx950), lane l = f0 + 4 f1 + 16 f2:
+//   A[i][k] at (f0, f2) = (i, k), B[k][j] at (f0, f2) = (j, k), D[i][j] at (f0, f2) = (j, i),
+// f1 the block.  A wave holds four elements (f1 = element slot, consecutive in x); for each
+// element and component, lane (f0, f2) keeps a column of four values along z in registers, so
+// contractions in z are register FMAs, and a contraction over f2 is one instruction per z value:
+//   mf_keep: table as A, data as B: contracts f2, the result index replaces f2, f0 kept;
+//   mf_swap: data as A, table as B: contracts f2, the result index goes to f0 and f0 to f2.
+// In both the lane supplies the table entry T[f0][f2] (T[q][m]: output q, input m).  Starting
+// from (f0, f2) = (x, y): y then x by mf_swap give the Gauss values with (f0, f2) = (qx, qy);
+// the x-derivative is mf_swap with the node-to-Gauss derivative table, the y-derivative mf_keep
+// with the Gauss-point derivative, the z-derivative a register contraction, so the gradient
+// components all end in one layout and the stress is pointwise.  The transposed contractions
+// run the same two swaps backwards, accumulating in the matrix cores' C operand.
+// Element contributions leave in z columns: the top value of a column is the bottom value of the
+// next element layer (same lane), kept in a register; node sums over the elements of a layer
+// go through a small LDS exchange in fixed order (deterministic, no atomics).
+__device__ __forceinline__ double mf_keep(double t, double v, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(t, v, c, 0, 0, 0);
+}
+__device__ __forceinline__ double mf_swap(double t, double v, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(v, t, c, 0, 0, 0);
+}
+
+enum : int { MT_B = 0, MT_D1 = 1, MT_DH = 2, MT_BT = 3, MT_D1T = 4 };
+// Entry (q, m) of an order-3 table with compile-time indices.
+template <int C>
+__device__ __forceinline__ double mt_entry(int q, int m) {
+  if constexpr (C == MT_B) return Bm<4, double>(q, m);
+  else if constexpr (C == MT_D1) return CT<4>::t.D1[q * 4 + m];
+  else if constexpr (C == MT_DH) return Dm<4, double>(q, m);
+  else if constexpr (C == MT_BT) return Bm<4, double>(m, q);
+  else return CT<4>::t.D1[m * 4 + q];
+}
+// The lane's entry T[f0][f2] of table C (selected among the 16 compile-time values).
+template <int C>
+__device__ inline double mt_lane(int f0, int f2) {
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v = (q == f0 && m == f2) ? mt_entry<C>(q, m) : v;
+  return v;
+}
+
+// Elements per block and LDS exchange layout of k_op_mfma: tile 8 x 4 elements (eight waves of
+// four elements consecutive in x), per element NC x 3 planes x 16 columns, padded.
+constexpr int MF_BX = 8, MF_BY = 4, MF_NE = MF_BX * MF_BY, MF_NT = 64 * MF_NE / 4;
+template <int NC>
+struct MfLds {
+  static constexpr int ES = NC * 3 * 16 + 4;   // doubles per element
+  static constexpr int BUF = MF_NE * ES;       // one exchange buffer
+};
+
+template <int NC, int F, int EP>
+__global__ void __launch_bounds__(MF_NT, 4)
+k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
+          double* __restrict__ y, const double* __restrict__ coef,
+          const double* __restrict__ sin_, double* __restrict__ face, const int add,
+          const Epi<double> ep) {
+  static_assert(Tile<4>::BX == MF_BX && Tile<4>::BY == MF_BY, "brick tile of order 3");
+  constexpr int k = 3, WX = k * MF_BX + 1, WY = k * MF_BY + 1, WP = WX * WY;
+  constexpr int ES = MfLds<NC>::ES, BUF = MfLds<NC>::BUF;
+  constexpr bool DIR = (F & F_DIR) != 0;
+  __shared__ double xch[2 * BUF];
+  const int N = G.N, M = G.M, nn = G.nn;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int f0 = lane & 3, f1 = (lane >> 2) & 3, f2 = lane >> 4;
+  const int el = wave * 4 + f1;                       // element in the block, el = ly BX + lx
+  const int lx = el % MF_BX, ly = el / MF_BX;
+  const int tx = blockIdx.x % G.nbx, ty = blockIdx.x / G.nbx, bz = blockIdx.y;
+  const int ex = tx * MF_BX + lx, ey = ty * MF_BY + ly;
+  const int X0 = tx * MF_BX * k, Y0 = ty * MF_BY * k;
+  const int X1 = X0 + k * MF_BX, Y1 = Y0 + k * MF_BY;
+  const int ez0 = bz * G.Bz, ez1 = min(N, ez0 + G.Bz);
+  const int Z0 = ez0 * k, Z1 = ez1 * k;
+  const bool valid = ex < N && ey < N;
+  const int gi = ex * k + f0, gj = ey * k + f2;       // node column of this lane
+  const bool bij = gi == 0 || gi == M - 1 || gj == 0 || gj == M - 1;
+  const int col = valid ? gi + M * gj : 0;
+  const double tB = mt_lane<MT_B>(f0, f2), tD1 = mt_lane<MT_D1>(f0, f2);
+  const double tDh = mt_lane<MT_DH>(f0, f2), tBT = mt_lane<MT_BT>(f0, f2);
+  const double tD1T = mt_lane<MT_D1T>(f0, f2);
+  const double w_out = Wg<4, double>(0), w_in = Wg<4, double>(1);  // Gauss weights, outer / inner
+  const double wxy = (f0 == 0 || f0 == 3 ? w_out : w_in) * (f2 == 0 || f2 == 3 ? w_out : w_in) * hh;
+  double uc[NC][4];       // node columns of the current layer (masked)
+  double carry[NC];       // contributions of the previous layer to its top plane
+#pragma unroll
+  for (int c = 0; c < NC; ++c) carry[c] = 0.0;
+  // input loader for node z-index gl of this lane's column (Dirichlet nodes and idle lanes: 0)
+  auto load_node = [&](int c, int gl) -> double {
+    const size_t j = (size_t)c * nn + (size_t)col + (size_t)M * M * gl;
+    double v;
+    if constexpr (EP == EPI_CHEB_ZERO) v = ep.gamma * ep.dinv[j] * ep.b[j];
+    else v = u[j];
+    if (sin_ != nullptr) v *= sin_[(size_t)col + (size_t)M * M * gl];
+    const bool live = valid && !(DIR && (bij || gl == 0 || gl == M - 1));
+    return live ? v : 0.0;
+  };
+#pragma unroll
+  for (int c = 0; c < NC; ++c) uc[c][0] = load_node(c, Z0);
+
+  // owner phase: the block's threads sum the contributions of the elements around each node
+  // column of the tile (fixed order) and store planes z = zb .. zb + np - 1
+  auto flush = [&](const double* buf, int zb, int np) {
+    for (int it = t; it < np * WP; it += MF_NT) {
+      const int l = it / WP, w = it - l * WP;
+      const int wx = w % WX, wy = w / WX;
+      const int gx = X0 + wx, gy = Y0 + wy;
+      if (gx >= M || gy >= M) continue;
+      double val[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) val[c] = 0.0;
+      const int qx = wx / k, rx = wx - qx * k, qy = wy / k, ry = wy - qy * k;
+      // candidates: (element, local index) in x and in y; local index k means the upper face
+#pragma unroll
+      for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+          const int ex_ = sx ? qx - 1 : qx, ax = sx ? k : rx;
+          const int ey_ = sy ? qy - 1 : qy, ay = sy ? k : ry;
+          if ((sx && (rx != 0 || qx == 0)) || (!sx && qx >= MF_BX)) continue;
+          if ((sy && (ry != 0 || qy == 0)) || (!sy && qy >= MF_BY)) continue;
+          const double* p = buf + (ey_ * MF_BX + ex_) * ES + l * 16 + ax + 4 * ay;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) val[c] += p[c * 48];
+        }
+      store_node<4, NC, double, DIR, EP>(G, gx, gy, zb + l, X0, Y0, Z0, X1, Y1, Z1, val, y, face,
+                                         add, ep);
+    }
+  };
+
+  for (int ez = ez0; ez < ez1; ++ez) {
+    const int e = valid ? ex + N * (ey + N * ez) : 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 1; r < 4; ++r) uc[c][r] = load_node(c, ez * k + r);
+    double cw[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      cw[r] = valid ? coef[(size_t)e * 64 + f0 + 4 * f2 + 16 * r] * wxy * Wg<4, double>(r) : 0.0;
+
+    // stresses at the lane's Gauss points (qx, qy) = (f0, f2), qz = register index
+    double sg[NC == 3 ? 6 : 3][4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double w[4], gx_[4], gy_[4], gz_[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) a += Bm<4, double>(q, l) * uc[c][l];
+        w[q] = a;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double p = mf_swap(tB, w[r], 0.0);          // (qy, x)
+        w[r] = mf_swap(tB, p, 0.0);                        // (qx, qy): Gauss values
+        gx_[r] = mf_swap(tD1, p, 0.0);                     // x-derivative
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gy_[r] = mf_keep(tDh, w[r], 0.0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a += Dm<4, double>(q, m) * w[m];
+        gz_[q] = a;
+      }
+      if constexpr (NC == 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          sg[0][r] = cw[r] * gx_[r];
+          sg[1][r] = cw[r] * gy_[r];
+          sg[2][r] = cw[r] * gz_[r];
+        }
+      } else {
+        // sg: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz (symmetric gradient times 2 mu w |J| (2/h)^2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (c == 0) {
+            sg[0][r] = 2.0 * cw[r] * gx_[r];
+            sg[3][r] = cw[r] * gy_[r];
+            sg[4][r] = cw[r] * gz_[r];
+          } else if (c == 1) {
+            sg[3][r] += cw[r] * gx_[r];
+            sg[1][r] = 2.0 * cw[r] * gy_[r];
+            sg[5][r] = cw[r] * gz_[r];
+          } else {
+            sg[4][r] += cw[r] * gx_[r];
+            sg[5][r] += cw[r] * gy_[r];
+            sg[2][r] = 2.0 * cw[r] * gz_[r];
+          }
+        }
+      }
+    }
+    // prefetch the bottom plane of the next layer (the top plane of this one)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uc[c][0] = uc[c][3];
+
+    double* buf = xch + (ez & 1) * BUF;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      constexpr int SX[3] = {0, 3, 4}, SY[3] = {3, 1, 5}, SZ[3] = {4, 5, 2};
+      const double* sx = sg[NC == 3 ? SX[c] : 0];
+      const double* sy = sg[NC == 3 ? SY[c] : 1];
+      const double* sz = sg[NC == 3 ? SZ[c] : 2];
+      double o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double tz = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tz += Dm<4, double>(q, r) * sz[q];
+        const double a = mf_swap(tBT, sx[r], 0.0);          // (y, qx)
+        double b = mf_swap(tD1T, sy[r], 0.0);
+        b = mf_swap(tBT, tz, b);
+        double oo = mf_swap(tD1T, a, 0.0);                   // (x, y)
+        o[r] = mf_swap(tBT, b, oo);
+      }
+      double v[4];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a += Bm<4, double>(q, l) * o[q];
+        v[l] = a;
+      }
+      v[0] += carry[c];
+      carry[c] = v[3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) buf[el * ES + c * 48 + l * 16 + f0 + 4 * f2] = v[l];
+    }
+    __syncthreads();
+    flush(buf, ez * k, k);
+  }
+  // top plane of the chunk
+  double* buf = xch + (ez1 & 1) * BUF;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) buf[el * ES + c * 48 + f0 + 4 * f2] = carry[c];
+  __syncthreads();
+  flush(buf, Z1, 1);
 }
 
 // Gradient alone (B^T p) node by node.  On the uniform brick mesh every element carries the same
@@ -1413,9 +1663,18 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
     T* face = static_cast<T*>(work);
     {
       ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
-      hipLaunchKernelGGL((k_op_brick<n, NC, T, F, MF, EP>), dim3(G.nbx * G.nby, G.nbz),
-                         dim3(BrickThreads<n>::NT), 0, st, D, hh, u, y, coef, pin, pout, sin, face,
-                         (int)add, ep);
+      bool done = false;
+      if constexpr (n == 4 && sizeof(T) == 8 && MF == 0 && (F & (F_BT | F_B)) == 0) {
+        if (matrix_core_ops.load(std::memory_order_relaxed)) {
+          hipLaunchKernelGGL((k_op_mfma<NC, F, EP>), dim3(G.nbx * G.nby, G.nbz), dim3(MF_NT), 0, st,
+                             D, (double)hh, u, y, coef, sin, face, (int)add, ep);
+          done = true;
+        }
+      }
+      if (!done)
+        hipLaunchKernelGGL((k_op_brick<n, NC, T, F, MF, EP>), dim3(G.nbx * G.nby, G.nbz),
+                           dim3(BrickThreads<n>::NT), 0, st, D, hh, u, y, coef, pin, pout, sin, face,
+                           (int)add, ep);
     }
     const size_t tot = (size_t)(G.nbx + G.nby + G.nbz - 3) * G.plane;
     if (tot > 0) {
@@ -2592,6 +2851,8 @@ __global__ void k_sub_mean(size_t n, double* __restrict__ x, const double* __res
 }  // namespace
 
 // ================================================================== launchers
+int set_matrix_core_ops(int on) { return matrix_core_ops.exchange(on ? 1 : 0); }
+
 double set_two_pass_limit(double mb) {
   const double prev = (double)two_pass_limit.load() / 1e6;
   const double b = std::min(std::max(mb, 0.0) * 1e6, (double)TWO_PASS_MAX_BYTES);

@@ -107,6 +107,7 @@ SIGNATURES = {
     "wb_mem_trim": (None, []),
     "wb_profile_enable": (None, [I]),
     "wb_set_two_pass_limit": (D, [D]),
+    "wb_set_matrix_core_ops": (I, [I]),
     "wb_profile_summary": (LL, [ctypes.c_char_p, LL, I]),
 }
 
@@ -242,6 +243,10 @@ def wb_profile_enable(on: bool):
 
 def wb_set_two_pass_limit(mb: float) -> float:
     return lib().wb_set_two_pass_limit(float(mb))
+
+
+def wb_set_matrix_core_ops(on: bool) -> bool:
+    return bool(lib().wb_set_matrix_core_ops(1 if on else 0))
 
 
 def wb_profile_summary(reset: bool = True):

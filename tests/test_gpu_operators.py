@@ -265,3 +265,39 @@ def test_apply_A_brick_and_two_pass_forms_match_assembled(N, k):
             assert _rel(host(y), want) < 1e-12, limit
     finally:
         wb.wb_set_two_pass_limit(prev)
+
+
+@pytest.mark.parametrize("N", [4, 11])
+def test_apply_A_q3_matrix_core_form_matches_assembled(N):
+    # order 3 above the two-pass size: the matrix-core brick kernel (x and y contractions on the
+    # FP64 matrix cores) and the LDS line kernel, each against the assembled oracle; N = 11 gives
+    # ragged tiles in x and y and one-layer brick chunks in z.  The matrix-core form sums each
+    # node's contributions in a fixed order, so repeated applies agree bit for bit.
+    wb = _wb()
+    om = fem.Mesh(N, 3)
+    rng = np.random.default_rng(N)
+    mu_q = 10.0 ** rng.uniform(-4, 4, (om.E, om.n ** 3))
+    m = wb.Mesh(N, 3)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(np.ones(om.n_nodes)))
+    u = random_vector(13, om.u_dof)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0.0
+    want = fem.assemble_A(om, mu_q) @ ui
+    want[om.vel_boundary] = 0.0
+    prev_limit = wb.wb_set_two_pass_limit(0.0)
+    prev_mc = wb.wb_set_matrix_core_ops(True)
+    try:
+        for on in (True, False):
+            wb.wb_set_matrix_core_ops(on)
+            y = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+            wb.wb_apply_A(m, v, dev(u), y)
+            got = host(y)
+            assert _rel(got, want) < 1e-12, on
+            assert np.all(got[om.vel_boundary] == 0.0)
+            if on:
+                y2 = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+                wb.wb_apply_A(m, v, dev(u), y2)
+                assert np.array_equal(host(y2), got)
+    finally:
+        wb.wb_set_two_pass_limit(prev_limit)
+        wb.wb_set_matrix_core_ops(prev_mc)

@@ -167,13 +167,17 @@ def test_fgmres_order_5_matches_oracle():
     assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(b)
 
 
-def test_brick_form_preconditioner_matches_oracle():
+@pytest.mark.parametrize("name,mc", [("n8k2", True), ("n4k3", True), ("n4k3", False)])
+def test_brick_form_preconditioner_matches_oracle(name, mc):
     # every A and Poisson apply in the brick form (the form large problems use): K_w, the
-    # V-cycles and the preconditioner against the oracle, and the FGMRES iteration count
+    # V-cycles and the preconditioner against the oracle, and the FGMRES iteration count; at
+    # order 3 both the matrix-core kernel and the LDS line kernel (their Chebyshev and residual
+    # epilogues included)
     wb = _wb()
-    w, st, P, m, v, _ = _pair("n8k2")
+    w, st, P, m, v, _ = _pair(name)
     om = st.mesh
     prev = wb.wb_set_two_pass_limit(0.0)
+    prev_mc = wb.wb_set_matrix_core_ops(mc)
     try:
         s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r)
         r = st.remove_mean(random_vector(31, om.p_dof))
@@ -198,6 +202,7 @@ def test_brick_form_preconditioner_matches_oracle():
         assert abs(rep.iters - it_oracle) <= 2, (rep.iters, it_oracle)
     finally:
         wb.wb_set_two_pass_limit(prev)
+        wb.wb_set_matrix_core_ops(prev_mc)
 
 
 @pytest.mark.parametrize("name", ["n8k2", "n4k5"])
