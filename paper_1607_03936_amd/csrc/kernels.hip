@@ -1103,33 +1103,53 @@ __device__ inline double mt_lane(int f0, int f2) {
   return v;
 }
 
-// Elements per block and LDS exchange layout of k_op_mfma: tile 8 x 4 elements (eight waves of
-// four elements consecutive in x), per element NC x 3 planes x 16 columns, padded.
-constexpr int MF_BX = 8, MF_BY = 4, MF_NE = MF_BX * MF_BY, MF_NT = 64 * MF_NE / 4;
+// Tile of k_op_mfma: 8 x 4 elements; a tile row is two waves of four elements consecutive in x
+// (f1 = element slot); eight waves.
+constexpr int MF_PX = 2, MF_BX = 4 * MF_PX, MF_BY = 8 / MF_PX, MF_NT = 512;
+
+// Neighbour exchange of k_op_mfma through LDS, per plane and component: the top row (f2 = 3) of
+// every wave's elements (16 values) for the row above, and the right column (f0 = 3) of the last
+// element of the left wave of a tile row (4 values) for the right wave.
 template <int NC>
 struct MfLds {
-  static constexpr int ES = NC * 3 * 16 + 4;   // doubles per element
-  static constexpr int BUF = MF_NE * ES;       // one exchange buffer
+  static constexpr int YW = NC * 3 * 16, XW = NC * 3 * 4;    // per wave
+  static constexpr int XOFF = 8 * YW, BUF = XOFF + 8 * XW;
 };
 
+// Value of lane - 1 within the lane's row of 16 (DPP row shift right by one).
+__device__ __forceinline__ double from_left(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x111, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int NC, int F, int EP>
-__global__ void __launch_bounds__(MF_NT, 4)
+__global__ void __launch_bounds__(MF_NT, 2)
 k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
           double* __restrict__ y, const double* __restrict__ coef,
           const double* __restrict__ sin_, double* __restrict__ face, const int add,
           const Epi<double> ep) {
   static_assert(Tile<4>::BX == MF_BX && Tile<4>::BY == MF_BY, "brick tile of order 3");
-  constexpr int k = 3, WX = k * MF_BX + 1, WY = k * MF_BY + 1, WP = WX * WY;
-  constexpr int ES = MfLds<NC>::ES, BUF = MfLds<NC>::BUF;
+  constexpr int k = 3, YW = MfLds<NC>::YW, XW = MfLds<NC>::XW, XOFF = MfLds<NC>::XOFF;
+  constexpr int BUF = MfLds<NC>::BUF;
   constexpr bool DIR = (F & F_DIR) != 0;
-  __shared__ double xch[2 * BUF];
+  __shared__ double ybuf[2 * BUF];
   const int N = G.N, M = G.M, nn = G.nn;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, px = wave % MF_PX, ly = wave / MF_PX;
   const int f0 = lane & 3, f1 = (lane >> 2) & 3, f2 = lane >> 4;
-  const int el = wave * 4 + f1;                       // element in the block, el = ly BX + lx
-  const int lx = el % MF_BX, ly = el / MF_BX;
-  const int tx = blockIdx.x % G.nbx, ty = blockIdx.x / G.nbx, bz = blockIdx.y;
-  const int ex = tx * MF_BX + lx, ey = ty * MF_BY + ly;
+  // XCD-aware tile order: workgroups go round-robin to the eight XCDs, so workgroup id maps to
+  // the tile L = (start of its XCD's range) + (id / 8) in x-fastest order; each XCD then owns a
+  // contiguous run of tiles, and the cache lines that neighbouring tiles share stay in one L2.
+  int tx, ty, bz;
+  {
+    const int T = G.nbx * G.nby * G.nbz, id = blockIdx.x, r = id & 7;
+    const int L = r * (T >> 3) + min(r, T & 7) + (id >> 3);
+    tx = L % G.nbx;
+    ty = (L / G.nbx) % G.nby;
+    bz = L / (G.nbx * G.nby);
+  }
+  const int ex = tx * MF_BX + 4 * px + f1, ey = ty * MF_BY + ly;
   const int X0 = tx * MF_BX * k, Y0 = ty * MF_BY * k;
   const int X1 = X0 + k * MF_BX, Y1 = Y0 + k * MF_BY;
   const int ez0 = bz * G.Bz, ez1 = min(N, ez0 + G.Bz);
@@ -1143,63 +1163,174 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
   const double tD1T = mt_lane<MT_D1T>(f0, f2);
   const double w_out = Wg<4, double>(0), w_in = Wg<4, double>(1);  // Gauss weights, outer / inner
   const double wxy = (f0 == 0 || f0 == 3 ? w_out : w_in) * (f2 == 0 || f2 == 3 ? w_out : w_in) * hh;
-  double uc[NC][4];       // node columns of the current layer (masked)
-  double carry[NC];       // contributions of the previous layer to its top plane
-#pragma unroll
-  for (int c = 0; c < NC; ++c) carry[c] = 0.0;
-  // input loader for node z-index gl of this lane's column (Dirichlet nodes and idle lanes: 0)
-  auto load_node = [&](int c, int gl) -> double {
-    const size_t j = (size_t)c * nn + (size_t)col + (size_t)M * M * gl;
-    double v;
-    if constexpr (EP == EPI_CHEB_ZERO) v = ep.gamma * ep.dinv[j] * ep.b[j];
-    else v = u[j];
-    if (sin_ != nullptr) v *= sin_[(size_t)col + (size_t)M * M * gl];
-    const bool live = valid && !(DIR && (bij || gl == 0 || gl == M - 1));
-    return live ? v : 0.0;
-  };
-#pragma unroll
-  for (int c = 0; c < NC; ++c) uc[c][0] = load_node(c, Z0);
 
-  // owner phase: the block's threads sum the contributions of the elements around each node
-  // column of the tile (fixed order) and store planes z = zb .. zb + np - 1
-  auto flush = [&](const double* buf, int zb, int np) {
-    for (int it = t; it < np * WP; it += MF_NT) {
-      const int l = it / WP, w = it - l * WP;
-      const int wx = w % WX, wy = w / WX;
-      const int gx = X0 + wx, gy = Y0 + wy;
-      if (gx >= M || gy >= M) continue;
-      double val[NC];
+  // Node sums.  A node column of the tile gets the contributions of at most four elements of the
+  // layer.  Within a wave, the lane in the element with the larger x (f0 = 0) adds its left
+  // neighbour's value (f0 = 3, previous slot: lane - 1 of the same row of 16).  Through LDS, the
+  // first element of the right wave of a tile row adds the right column of the left wave's last
+  // element, and the lane in the element with the larger y (f2 = 0) adds the row below (f2 = 3,
+  // summed within its wave); the one node column that joins four elements of two waves and two
+  // rows also adds the corner of the left wave below.  The lane that ends up with a column's sum
+  // owns it: f0 < 3 or the tile's last slot, f2 < 3 or the tile's last row.
+  const bool xrecv = f0 == 0 && f1 > 0;
+  const bool xsend = px < MF_PX - 1 && f0 == 3 && f1 == 3, xcross = px > 0 && f0 == 0 && f1 == 0;
+  const bool ysend = f2 == 3 && ly < MF_BY - 1, yrecv = f2 == 0 && ly > 0;
+  const bool diag = xcross && f2 == 0 && ly > 0;
+  const bool owner = (f0 < 3 || (px == MF_PX - 1 && f1 == 3)) && (f2 < 3 || ly == MF_BY - 1) &&
+                     gi < M && gj < M;
+  const int yoff = wave * YW + f0 + 4 * f1;                 // this wave's top row
+  const int xoff = XOFF + wave * XW + f2;                   // this (left) wave's right column
+  // destination of the owner's values on planes inside the chunk and off the domain boundary in
+  // z: a node store (with the epilogue), a brick-face slot, a Dirichlet zero, or nothing (another
+  // brick emits it); the chunk's first and last planes take the general store_node
+  enum { K_NODE = 0, K_FACE = 1, K_ZERO = 2, K_SKIP = 3 };
+  int kind = K_SKIP, base = 0;
+  {
+    constexpr int KX = k * MF_BX, KY = k * MF_BY;
+    const bool lx = gi == X0 && X0 > 0, ux = gi == X1 && X1 < M - 1;
+    const bool lyb = gj == Y0 && Y0 > 0, uyb = gj == Y1 && Y1 < M - 1;
+    if (!owner) kind = K_SKIP;
+    else if (DIR && bij) kind = (lx || lyb) ? K_SKIP : K_ZERO;
+    else if (!(lx || ux || lyb || uyb)) kind = K_NODE;
+    else {
+      kind = K_FACE;
+      const int sl = (lx ? 1 : 0) + 2 * (lyb ? 1 : 0);
+      if (lx || ux) base = (sl * (G.nbx - 1) + gi / KX - 1) * M * M + gj;
+      else base = G.fy + (sl * (G.nby - 1) + gj / KY - 1) * M * M + gi;
+    }
+  }
+  const int colg = gi + M * gj;
+  auto store = [&](const double (&val)[NC], int gz, bool general) {
+    if (general) {
+      if (owner)
+        store_node<4, NC, double, DIR, EP>(G, gi, gj, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add,
+                                           ep);
+    } else if (kind == K_NODE) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) val[c] = 0.0;
-      const int qx = wx / k, rx = wx - qx * k, qy = wy / k, ry = wy - qy * k;
-      // candidates: (element, local index) in x and in y; local index k means the upper face
+      for (int c = 0; c < NC; ++c)
+        emit<EP>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, val[c], y, add);
+    } else if (kind == K_FACE) {
 #pragma unroll
-      for (int sy = 0; sy < 2; ++sy)
+      for (int c = 0; c < NC; ++c) face[(size_t)c * G.per_comp + base + (size_t)M * gz] = val[c];
+    } else if (kind == K_ZERO) {
 #pragma unroll
-        for (int sx = 0; sx < 2; ++sx) {
-          const int ex_ = sx ? qx - 1 : qx, ax = sx ? k : rx;
-          const int ey_ = sy ? qy - 1 : qy, ay = sy ? k : ry;
-          if ((sx && (rx != 0 || qx == 0)) || (!sx && qx >= MF_BX)) continue;
-          if ((sy && (ry != 0 || qy == 0)) || (!sy && qy >= MF_BY)) continue;
-          const double* p = buf + (ey_ * MF_BX + ex_) * ES + l * 16 + ax + 4 * ay;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) val[c] += p[c * 48];
-        }
-      store_node<4, NC, double, DIR, EP>(G, gx, gy, zb + l, X0, Y0, Z0, X1, Y1, Z1, val, y, face,
-                                         add, ep);
+      for (int c = 0; c < NC; ++c)
+        emit<EP>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, 0.0, y, add);
     }
   };
-
-  for (int ez = ez0; ez < ez1; ++ez) {
-    const int e = valid ? ex + N * (ey + N * ez) : 0;
+  // sums the np planes of v across the tile (v holds this lane's element contributions) and stores
+  // them at z = zb + l; the first plane through store_node when first_general
+  auto node_sums = [&](double (&v)[NC][3], int np, int zb, bool first_general, double* buf) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int r = 1; r < 4; ++r) uc[c][r] = load_node(c, ez * k + r);
+      for (int l = 0; l < 3; ++l)
+        if (l < np) {
+          const double w = from_left(v[c][l]);
+          if (xrecv) v[c][l] += w;
+        }
+    if (ysend) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          if (l < np) buf[yoff + (c * 3 + l) * 16] = v[c][l];
+    }
+    if (xsend) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          if (l < np) buf[xoff + (c * 3 + l) * 4] = v[c][l];
+    }
+    __syncthreads();
+    if (xcross) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          if (l < np) v[c][l] += buf[xoff - XW + (c * 3 + l) * 4];
+    }
+    if (yrecv) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          if (l < np) v[c][l] += buf[yoff - MF_PX * YW + (c * 3 + l) * 16];
+    }
+    if (diag) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          if (l < np) v[c][l] += buf[xoff - XW - MF_PX * XW + 3 + (c * 3 + l) * 4];
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      if (l < np) {
+        double val[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) val[c] = v[c][l];
+        store(val, zb + l, l == 0 && first_general);
+      }
+  };
+
+  double uc[NC][4];         // node columns of the current layer (masked)
+  double carry[NC];         // contributions of the previous layer to its top plane
+#pragma unroll
+  for (int c = 0; c < NC; ++c) carry[c] = 0.0;
+  // raw loads of node z-index gl of this lane's column (in-bounds for idle lanes: column 0),
+  // masked afterwards (Dirichlet nodes and idle lanes: 0)
+  auto raw_node = [&](int c, int gl) -> double {
+    const size_t j = (size_t)c * nn + (size_t)col + (size_t)M * M * gl;
+    if constexpr (EP == EPI_CHEB_ZERO) return ep.gamma * ep.dinv[j] * ep.b[j];
+    else return u[j];
+  };
+  auto live_node = [&](int gl) -> bool { return valid && !(DIR && (bij || gl == 0 || gl == M - 1)); };
+  double cq[4];             // coefficient of the current layer at the lane's Gauss points
+  // loads of one layer (nodes 1..3 of the column, coefficient); two sets, so that the loads of
+  // the layer after next are in flight during a whole layer
+  struct LBuf {
+    double u[NC][3], c[4];
+  };
+  auto load_layer = [&](int ez, LBuf& b) {
+    const size_t eb = (size_t)(valid ? ex + N * (ey + N * ez) : 0) * 64 + f0 + 4 * f2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b.c[r] = coef[eb + 16 * r];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 1; r < 4; ++r) b.u[c][r - 1] = raw_node(c, ez * k + r);
+  };
+  auto take_layer = [&](int ez, const LBuf& b) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cq[r] = b.c[r];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+      const int gl = ez * k + r;
+      const double sc = sin_ != nullptr ? sin_[(size_t)col + (size_t)M * M * gl] : 1.0;
+      const bool lv = live_node(gl);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uc[c][r] = lv ? b.u[c][r - 1] * sc : 0.0;
+    }
+  };
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double sc = sin_ != nullptr ? sin_[(size_t)col + (size_t)M * M * Z0] : 1.0;
+    uc[c][0] = live_node(Z0) ? raw_node(c, Z0) * sc : 0.0;
+  }
+  LBuf lb0, lb1;
+  load_layer(ez0, lb0);
+  take_layer(ez0, lb0);
+  if (ez0 + 1 < ez1) load_layer(ez0 + 1, lb0);
+
+  // one element layer: `next` holds the loads of layer ez + 1 (in flight), `fill` receives those
+  // of layer ez + 2
+  auto layer = [&](const int ez, const LBuf& next, LBuf& fill) {
+    if (ez + 2 < ez1) load_layer(ez + 2, fill);
     double cw[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      cw[r] = valid ? coef[(size_t)e * 64 + f0 + 4 * f2 + 16 * r] * wxy * Wg<4, double>(r) : 0.0;
+    for (int r = 0; r < 4; ++r) cw[r] = valid ? cq[r] * wxy * Wg<4, double>(r) : 0.0;
 
     // stresses at the lane's Gauss points (qx, qy) = (f0, f2), qz = register index
     double sg[NC == 3 ? 6 : 3][4];
@@ -1255,11 +1386,11 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
         }
       }
     }
-    // prefetch the bottom plane of the next layer (the top plane of this one)
+    // the bottom plane of the next layer is the top plane of this one
 #pragma unroll
     for (int c = 0; c < NC; ++c) uc[c][0] = uc[c][3];
 
-    double* buf = xch + (ez & 1) * BUF;
+    double v3[NC][3];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       constexpr int SX[3] = {0, 3, 4}, SY[3] = {3, 1, 5}, SZ[3] = {4, 5, 2};
@@ -1286,20 +1417,23 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
         for (int q = 0; q < 4; ++q) a += Bm<4, double>(q, l) * o[q];
         v[l] = a;
       }
-      v[0] += carry[c];
+      v3[c][0] = v[0] + carry[c];
+      v3[c][1] = v[1];
+      v3[c][2] = v[2];
       carry[c] = v[3];
-#pragma unroll
-      for (int l = 0; l < 3; ++l) buf[el * ES + c * 48 + l * 16 + f0 + 4 * f2] = v[l];
     }
-    __syncthreads();
-    flush(buf, ez * k, k);
+    node_sums(v3, 3, ez * k, ez == ez0, ybuf + (ez & 1) * BUF);
+    if (ez + 1 < ez1) take_layer(ez + 1, next);
+  };
+  for (int ez = ez0; ez < ez1; ez += 2) {
+    layer(ez, lb0, lb1);
+    if (ez + 1 < ez1) layer(ez + 1, lb1, lb0);
   }
   // top plane of the chunk
-  double* buf = xch + (ez1 & 1) * BUF;
+  double vt[NC][3];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) buf[el * ES + c * 48 + f0 + 4 * f2] = carry[c];
-  __syncthreads();
-  flush(buf, Z1, 1);
+  for (int c = 0; c < NC; ++c) vt[c][0] = vt[c][1] = vt[c][2] = carry[c];
+  node_sums(vt, 1, Z1, true, ybuf + (ez1 & 1) * BUF);
 }
 
 // Gradient alone (B^T p) node by node.  On the uniform brick mesh every element carries the same
@@ -1666,7 +1800,7 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
       bool done = false;
       if constexpr (n == 4 && sizeof(T) == 8 && MF == 0 && (F & (F_BT | F_B)) == 0) {
         if (matrix_core_ops.load(std::memory_order_relaxed)) {
-          hipLaunchKernelGGL((k_op_mfma<NC, F, EP>), dim3(G.nbx * G.nby, G.nbz), dim3(MF_NT), 0, st,
+          hipLaunchKernelGGL((k_op_mfma<NC, F, EP>), dim3(G.nbx * G.nby * G.nbz), dim3(MF_NT), 0, st,
                              D, (double)hh, u, y, coef, sin, face, (int)add, ep);
           done = true;
         }
