@@ -54,6 +54,11 @@ class Workload:
     def p_dof(self) -> int:
         return self.N ** 3 * self.k * (self.k + 1) * (self.k + 2) // 6
 
+    def describe(self) -> str:
+        return (f"{self.name}: {self.N}^3 elements, Q{self.k} x P{self.k - 1}-disc, {self.n_sinkers} "
+                f"seeded sinkers, delta {self.delta:g}, omega {self.omega:g}, DR {self.dr:g}, "
+                f"a_r {self.a_r:g}, FGMRES(100) to 1e-6")
+
 
 def default_a_r(N: int, k: int) -> float:
     """Right boundary amplification schedule max(1, (N/16) * 2^(k-2)).
@@ -88,3 +93,16 @@ def sinker_centers(seed: int, n: int) -> np.ndarray:
 def random_vector(seed: int, size: int) -> np.ndarray:
     """Uniform [-1, 1) test vector, float64."""
     return np.random.default_rng(seed + 7919).uniform(-1.0, 1.0, size)
+
+
+# Learned coarse correction: training fields from seeds 1000..2999 and validation fields from
+# seeds 3000..3099 (disjoint from the evaluation seeds 1..5), each with the workload's sinker count.
+TRAIN_SEEDS = range(1000, 3000)
+VALID_SEEDS = range(3000, 3100)
+
+
+def learned_fields(w: Workload, n_train: int = len(TRAIN_SEEDS), n_valid: int = len(VALID_SEEDS)):
+    """Sinker centres of the training and validation fields of workload w."""
+    train = [sinker_centers(s, w.n_sinkers) for s in list(TRAIN_SEEDS)[:n_train]]
+    valid = [sinker_centers(s, w.n_sinkers) for s in list(VALID_SEEDS)[:n_valid]]
+    return train, valid
