@@ -31,13 +31,21 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-# c1 (two levels), an h-coarsened Q2 case, and Q3, Q4 and Q5 cases
+# c1 (two levels), an h-coarsened Q2 case, and Q3, Q4 and Q5 cases; then small meshes with the
+# larger workloads' contrasts and sinker sets: DR 1e10 at Q2 (8 sinkers), the 64^3 Q3 parameters
+# (48 sinkers, delta 300, omega 0.04, DR 1e10) on 4^3, the 48^3 Q2 parameters (32 sinkers, DR 1e10)
+# on 12^3, whose h-hierarchy ends at 6^3 like 48^3, and the 16^3 Q4 parameters (24 sinkers, omega
+# 0.05, DR 1e8) on 4^3.  At these contrasts the coefficient coarsening clamps.
 SETUPS = {
     "c1": WORKLOADS["c1"],
     "n8k2": custom("n8k2", 8, 2, n_sinkers=8, dr=1e6, a_r=2.0, seed=5),
     "n4k3": custom("n4k3", 4, 3, n_sinkers=4, dr=1e4, a_r=2.0, seed=6),
     "n4k4": custom("n4k4", 4, 4, n_sinkers=3, dr=1e4, a_l=2.0, a_r=1.0, seed=7),
     "n4k5": custom("n4k5", 4, 5, n_sinkers=3, dr=1e4, a_r=2.0, seed=8),
+    "n8k2dr10": custom("n8k2dr10", 8, 2, n_sinkers=8, dr=1e10, a_r=2.0, seed=9),
+    "n4k3c5": custom("n4k3c5", 4, 3, n_sinkers=48, delta=300.0, omega=0.04, dr=1e10, a_r=2.0, seed=10),
+    "n12k2c4": custom("n12k2c4", 12, 2, n_sinkers=32, dr=1e10, seed=11),
+    "n4k4c3": custom("n4k4c3", 4, 4, n_sinkers=24, omega=0.05, dr=1e8, seed=12),
 }
 
 _cache = {}
@@ -142,6 +150,34 @@ def test_fgmres_solution_matches_direct_solve(name):
     _, it_oracle, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6)
     assert rep6.rel_res <= 1e-6
     assert abs(rep6.iters - it_oracle) <= 2, (rep6.iters, it_oracle)
+
+
+@pytest.mark.parametrize("name", ["n8k2dr10", "n4k3c5", "n12k2c4", "n4k4c3"])
+def test_fgmres_high_contrast_matches_oracle(name):
+    # contrasts 1e8 - 1e10: a direct solve is no reference there (condition numbers near 1/eps)
+    # and relative residuals near 1e-11 are out of reach in FP64, so the solve at the paper's
+    # tolerance is checked by its iteration count against the oracle's FGMRES and by its residual
+    # under the oracle's own operator
+    wb = _wb()
+    w, st, P, m, v, _ = _pair(name)
+    om = st.mesh
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    assert _rel(host(f)[st.idx], st.F) < 1e-13
+    u = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    p = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    # coarse meshes do not resolve these sinker sets and need hundreds of iterations
+    s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, max_iter=5000)
+    rep = s.solve(f, u, p)
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    _, it_oracle, _ = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-6, max_iter=5000)
+    assert rep.rel_res <= 1e-6
+    print(f"{name}: {rep.iters} FGMRES iterations (oracle {it_oracle})")
+    assert abs(rep.iters - it_oracle) <= max(2, it_oracle // 20), (rep.iters, it_oracle)
+    uh, ph = host(u), host(p)
+    assert np.all(uh[om.vel_boundary] == 0.0)
+    res = b - st.stokes_matvec(np.concatenate([uh[st.idx], ph]))
+    assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(b)
 
 
 def test_fgmres_order_5_matches_oracle():
@@ -467,3 +503,92 @@ def test_solver_rejects_invalid_options():
         with pytest.raises(wb.WbError) as ei:
             wb.Solver(m, v, **kw)
         assert ei.value.code == wb.WB_EINVAL and msg in str(ei.value), (kw, str(ei.value))
+
+
+def _oracle_subsolve(st, P, which, b):
+    """The oracle's GMRES on A (which = 0) or K_l / K_r (1 / 2) with one V-cycle as preconditioner."""
+    if which == 0:
+        return solver.fgmres(lambda x: st.A @ x, b, P.a_vcycle, rtol=1e-6, max_iter=500)
+    K, side = (st.Kl, "l") if which == 1 else (st.Kr, "r")
+    return solver.fgmres(lambda x: K @ x, st.remove_mean(b), lambda v: P.k_vcycle(side, v), rtol=1e-6,
+                         max_iter=500)
+
+
+@pytest.mark.parametrize("name", ["n8k2", "n4k3", "n8k2dr10"])
+def test_subsolve_matches_oracle(name):
+    # the component sub-solves of the paper's Table 3: GMRES on A u = f and on K_l, K_r p = g, each
+    # with one V-cycle as preconditioner, against the oracle's GMRES with its V-cycles
+    w, st, P, m, v, s = _pair(name)
+    om = st.mesh
+    ru = random_vector(41, om.u_dof)
+    ru[om.vel_boundary] = 0.0
+    x = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    rep = s.subsolve(0, dev(ru), x)
+    xo, it_o, _ = _oracle_subsolve(st, P, 0, ru[st.idx])
+    assert rep.rel_res <= 1e-6
+    assert abs(rep.iters - it_o) <= 2, (rep.iters, it_o)
+    assert _rel(host(x)[st.idx], xo) < 1e-5
+    rp = random_vector(42, om.p_dof)
+    xp = torch.empty(om.p_dof, dtype=torch.float64, device="cuda")
+    for which in (1, 2):
+        rep = s.subsolve(which, dev(rp), xp)
+        xo, it_o, _ = _oracle_subsolve(st, P, which, rp)
+        assert rep.rel_res <= 1e-6
+        assert abs(rep.iters - it_o) <= 2, (which, rep.iters, it_o)
+        assert _rel(host(xp), st.remove_mean(xo)) < 1e-5
+
+
+def test_subsolve_iterations_at_32cubed_q2():
+    # the Table 3 setting (k = 2, 32^3, 16 sinkers, DR 1e6, a_r = 2) with seeded centres: the
+    # paper reports 18 GMRES iterations for A and 7 for K_r; different centres, so only
+    # convergence and a band around those counts are checked (parity unpinned)
+    wb = _wb()
+    w = WORKLOADS["c2"]
+    m = wb.Mesh(w.N, w.k)
+    v = wb.Viscosity.sinker(m, w.centers(), w.delta, w.omega, w.mu_min, w.mu_max)
+    s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r)
+    om = fem.Mesh(w.N, w.k)
+    ru = random_vector(43, m.u_len)
+    ru[om.vel_boundary] = 0.0
+    ru = dev(ru)
+    x = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    rep_a = s.subsolve(0, ru, x)
+    rp = dev(random_vector(44, m.p_len))
+    xp = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    rep_k = s.subsolve(2, rp, xp)
+    print(f"32^3 Q2 sub-solves: A {rep_a.iters} iterations, K_r {rep_k.iters} iterations")
+    assert rep_a.rel_res <= 1e-6 and rep_k.rel_res <= 1e-6
+    assert 2 <= rep_a.iters <= 36 and 2 <= rep_k.iters <= 14
+
+
+def test_solution_matches_oracle_fgmres_at_32cubed_q2():
+    # the 32^3 Q2 workload (16 sinkers, DR 1e6) in full: the GPU FP64 solve against the oracle's
+    # FGMRES driven to relative residual 1e-11 (paper eq. 2, the discrete solution)
+    wb = _wb()
+    w = WORKLOADS["c2"]
+    c = w.centers()
+    st = solver.Stokes(w.N, w.k, c, w.delta, w.omega, w.mu_min, w.mu_max, a_l=w.a_l, a_r=w.a_r)
+    P = solver.Preconditioner(st)
+    b = np.concatenate([st.F, np.zeros(st.np_)])
+    xr, it_r, hist = solver.fgmres(st.stokes_matvec, b, P.apply, rtol=1e-11, max_iter=400)
+    assert hist[-1] <= 1e-11
+    u_ref, p_ref = xr[:st.nu], st.remove_mean(xr[st.nu:])
+    m = wb.Mesh(w.N, w.k)
+    v = wb.Viscosity.sinker(m, c, w.delta, w.omega, w.mu_min, w.mu_max)
+    f = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, c, w.delta, w.omega, w.beta, f)
+    u = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    p = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    errs = {}
+    for rtol in (1e-6, 1e-7, 1e-8):
+        s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, rtol=rtol)
+        rep = s.solve(f, u, p)
+        assert rep.rel_res <= rtol
+        uh, ph = host(u)[st.idx], st.remove_mean(host(p))
+        errs[rtol] = (np.linalg.norm(uh - u_ref) / np.linalg.norm(u_ref),
+                      np.linalg.norm(ph - p_ref) / np.linalg.norm(p_ref), rep.iters)
+        del s
+    print("32^3 Q2 solution error against the oracle (rtol: du, dp, iterations):", errs)
+    # at the paper's tolerance the solution is within 1e-4; driven to 1e-8 it is within 1e-6
+    assert max(errs[1e-6][:2]) <= 1e-4
+    assert max(errs[1e-8][:2]) <= 1e-6
