@@ -320,8 +320,8 @@ def learned_form(run, u64, p64, plain):
     s = wb.Solver(run.mesh, run.visc(), a_l=w.a_l, a_r=w.a_r, use_learned=1)
     train, valid = learned_fields(w)
     t0 = time.perf_counter()
-    tr = s.learned_train(train + valid, n_valid=len(valid), pairs_per_field=1, epochs=12, batch=16,
-                         lr=1e-3, delta=w.delta, omega=w.omega, mu_min=w.mu_min, mu_max=w.mu_max)
+    tr = s.learned_train(train + valid, n_valid=len(valid), pairs_per_field=1, epochs=20, batch=16,
+                         lr=1e-4, delta=w.delta, omega=w.omega, mu_min=w.mu_min, mu_max=w.mu_max)
     t_train = time.perf_counter() - t0
     u = torch.empty_like(u64)
     p = torch.empty_like(p64)
@@ -333,7 +333,8 @@ def learned_form(run, u64, p64, plain):
     tv = time.perf_counter() - t0
     du = (torch.linalg.norm(u - u64) / torch.linalg.norm(u64)).item()
     out = {"solve_s": round(tv, 4), "iters": rep.iters, "rel_res": rep.rel_res,
-           "converged": rep.rel_res <= 1e-6, "accepted_steps": rep.learned_used,
+           "converged": rep.rel_res <= 1e-6, "learned_reduction_at_lc": rep.learned_reduction,
+           "accepted_steps": rep.learned_used,
            "rejected_or_switched": rep.fell_back, "rel_err_u_vs_fp64": du,
            "device_bytes": int(rep.device_bytes),
            "vs_plain": {"iters": plain["iters"], "solve_s": plain["solve_s"]},

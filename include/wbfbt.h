@@ -30,7 +30,8 @@
  *    points q = qx + n (qy + n qz), n = k+1.
  *  - Every call returns a wb_status; on failure wb_last_error() gives a
  *    thread-local message.  No partial results are guaranteed on failure.
- *  - k in {1,2,3,4} for operator applies, k in {2,3,4} for Stokes solves.
+ *  - k in {1,...,5} for operator applies, k in {2,...,5} for Stokes solves (the BF16
+ *    matrix-core precision forms: k <= 4).
  */
 #ifndef WBFBT_H
 #define WBFBT_H
@@ -115,6 +116,13 @@ typedef struct {
   int fell_back;          /* learned correction rejected in favour of the V-cycle  */
   int learned_used;       /* learned correction applications that were accepted    */
   size_t device_bytes;    /* device memory held by the solver                      */
+  double learned_reduction; /* |r - alpha A delta| / |r| of the learned correction's
+                             first application in the last solve (1 if none)       */
+  const double* history;  /* HOST, owned by the solver, valid until its next solve or
+                             destruction: the relative residual estimate of FGMRES
+                             after iterations 1 .. history_len (wb_solve), or of
+                             GMRES (wb_subsolve)                                    */
+  int history_len;
 } wb_report;
 
 WB_API void wb_opts_default(wb_opts* o);
@@ -221,20 +229,24 @@ WB_API wb_status wb_solver_query(wb_solver* s, int what, int level, double* out_
 WB_API wb_status wb_solver_levels(wb_solver* s, int which, int* nlevels, int* Ns, int* ks, double* lmax);
 
 /* ---- learned coarse correction (velocity V-cycle, level Q1 on N/2) ----
- * The paper has no learned component; this is the data-driven counterpart of its multigrid
- * smoothing (Sec. 6) used as an optional extra step.  At the velocity level lc = Q1 on N/2
- * elements per direction (M = N/2 + 1 nodes per direction), after the plain V-cycle there:
+ * The paper has no learned component; this is a data-driven stand-in for the coarse-grid
+ * correction of the velocity multigrid (Sec. 6).  At the velocity level lc = Q1 on N/2 elements
+ * per direction (M = N/2 + 1 nodes per direction), the V-cycle pre-smooths, forms
  *   r = b - A_c x,  rho = rms(r),  delta = rho N_theta(f, r / rho) / diag(A_c)  (0 on the boundary),
- *   x <- x + alpha delta,  alpha = clip((r, A_c delta) / (A_c delta, A_c delta), 0, 2),
- * so the step never increases the residual and alpha = 0 is the plain V-cycle (a rejected step).
+ *   x <- x + alpha delta,  alpha = clip((r, A_c delta) / (A_c delta, A_c delta), 0, 2)
+ * in place of the restriction, the recursion below lc and the prolongation, and post-smooths.
  * f is the node feature (mean log10 mu of the adjacent elements, / 5).  N_theta: FP32 3x3x3
  * convolutions with zero padding, 4 -> 16 -> 16 -> 16 -> 3 channels, leaky ReLU (slope 0.1).
- * It is used by wb_solve when opts.use_learned = 1 and the network is trained or set; FGMRES
- * switches it off for the rest of a solve when the residual falls by less than half over 20
- * iterations (wb_report.fell_back counts rejected steps plus such a switch-off). */
+ * It is used by wb_solve when opts.use_learned = 1 and the network is trained or set.  The plain
+ * V-cycle is the fallback: the solve's first preconditioner apply checks the correction
+ * (wb_report.learned_reduction = |r - alpha A_c delta| / |r| there) and keeps it only if that is
+ * at most 0.9, otherwise it repeats the apply with the plain V-cycle and uses it for the rest of
+ * the solve; FGMRES also switches to the plain V-cycle when the residual falls by less than half
+ * over 20 iterations.  wb_report.fell_back counts rejected steps (alpha = 0) and such switches. */
 typedef struct {
   int pairs_per_field;    /* training pairs per viscosity field (8)                       */
-  int vcycles;            /* plain V-cycles applied to each random start error (1)        */
+  int vcycles;            /* pre-smoothing passes (the V-cycle's Chebyshev smoother at lc)
+                             applied to each random start error (1)                       */
   int epochs;             /* passes over the training pairs (20)                          */
   int batch;              /* pairs per Adam step (8)                                      */
   double lr;              /* Adam step size (1e-3; beta 0.9, 0.999, eps 1e-8)             */
@@ -254,10 +266,11 @@ typedef struct {
 WB_API void wb_train_opts_default(wb_train_opts* o);
 /* Train the network of solver s on its GPU.  Field f has n_sinkers[f] sinker centers, stored
  * after those of fields 0..f-1 in centers_host ([sum n_sinkers][3], HOST).  For each field the
- * library evaluates the sinker viscosity on the solver's mesh, coarsens it to levels lc.. like
- * the solver's own hierarchy (diagonals, Chebyshev bounds per field; the coarsest direct solve
- * is the solver's), and forms pairs: e = (I - V A_c)^vcycles e0 with e0 a splitmix64 field,
- * r = A_c e, target d e / rho and weight rho^2 / (d sum_j d_j e_j^2) (d = diag A_c) for the loss
+ * library evaluates the sinker viscosity on the solver's mesh, coarsens it to level lc like the
+ * solver's own hierarchy (that field's own diagonal, Chebyshev bounds and, where the solver
+ * assembles lc, stencil), and forms pairs: e = (I - S A_c)^vcycles e0 with e0 a splitmix64
+ * field and S the pre-smoother at lc (the error left for the coarse correction), r = A_c e,
+ * target d e / rho and weight rho^2 / (d sum_j d_j e_j^2) (d = diag A_c) for the loss
  * (1/B) sum w (N_theta - t)^2 (N_theta = 0 scores 1).  Then Adam over shuffled batches, from
  * fresh He-uniform weights with a zero output layer.
  * Synchronizes the stream.  WB_EUNSUPPORTED if the mesh has no level Q1 on N/2 above the

@@ -193,14 +193,20 @@ class Hierarchy:
             pinv = np.linalg.pinv(Ad)
             self.coarse = lambda b: pinv @ b
 
-    def vcycle(self, b, li=0):
+    def vcycle(self, b, li=0, learned=None):
+        """One V-cycle from level li.  learned = (lc, step): at level lc the coarse-grid
+        correction (restriction, the cycle below, prolongation) is replaced by x += step(r), r the
+        residual after pre-smoothing (the learned coarse correction; no paper content)."""
         L = self.levels[li]
         if li == len(self.levels) - 1:
             return self.coarse(b)
         x = chebyshev(L.A, L.dinv, b, None, L.lmin, L.lmax, self.degree, x_zero=True)
         r = b - L.A @ x
-        ec = self.vcycle(L.P.T @ r, li + 1)
-        x = x + L.P @ ec
+        if learned is not None and li == learned[0]:
+            x = x + learned[1](r)
+        else:
+            ec = self.vcycle(L.P.T @ r, li + 1, learned)
+            x = x + L.P @ ec
         return chebyshev(L.A, L.dinv, b, x, L.lmin, L.lmax, self.degree)
 
 

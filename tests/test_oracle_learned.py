@@ -117,3 +117,23 @@ def test_guarded_correction_never_increases_the_residual():
     e = np.linalg.solve(A.toarray(), r)
     Ad = A @ e
     assert abs(float(r @ Ad) / float(Ad @ Ad) - 1.0) < 1e-10
+
+
+def test_vcycle_learned_hook_replaces_the_coarse_correction():
+    # with the hook set to the plain coarse-grid correction of level lc (restriction, the cycle
+    # below, prolongation), the hooked V-cycle is the plain V-cycle; with a zero correction it is
+    # pre- and post-smoothing alone
+    import numpy as np
+
+    from oracle import fem, solver
+    m = fem.Mesh(8, 2)
+    mu = np.exp(np.random.default_rng(3).uniform(-2, 2, (m.E, m.n ** 3)))
+    Hh = solver.Hierarchy(8, 2, mu, "velocity", 1000)
+    lc = 1
+    L = Hh.levels[lc]
+    b = np.random.default_rng(4).uniform(-1, 1, Hh.levels[0].A.shape[0])
+    plain = Hh.vcycle(b)
+    same = Hh.vcycle(b, 0, (lc, lambda r: L.P @ Hh.vcycle(L.P.T @ r, lc + 1)))
+    assert np.array_equal(plain, same)
+    zero = Hh.vcycle(b, 0, (lc, lambda r: np.zeros_like(r)))
+    assert np.abs(zero - plain).max() > 1e-6 * np.abs(plain).max()
