@@ -157,6 +157,17 @@ WB_API void wb_visc_destroy(wb_visc* v);
 WB_API wb_status wb_rhs_sinker(const wb_mesh* m, const double* centers_host, int n_sinkers,
                                double delta, double omega, double beta, double* f_dev, void* stream);
 
+/* wb_apply_A without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same operator and
+ * kernels as wb_apply_A, with the library's fixed per-device workspace of 64 MiB (a device array
+ * each GPU holds until the process ends) instead of the mesh's allocated one.  Meshes whose
+ * workspace does not fit are rejected with WB_EINVAL (the two-pass form is used only while its
+ * element buffer fits, the brick form otherwise: 32^3 Q2, 16^3 Q4 and 48^3 Q2 fit, 64^3 Q3 does
+ * not).  No contents need to survive between calls; calls that overlap on one GPU (other
+ * threads or streams) race on the workspace and must be ordered by the caller. */
+WB_API wb_status wb_apply_A_noalloc(const wb_mesh* mesh, const wb_visc* visc, const double* u,
+                                    double* y, void* stream);
+
 /* ---- discrete operators of eq. (2), matrix-free ----
  * A: viscous stress, (A u)_i = sum_e int_e 2 mu eps(u) : eps(phi_i)   (Sec. 1.2, 3.1)
  * B: divergence, (B u)_{e,m} = -int_e psi_m div u  (B = -div, Sec. 3.1)

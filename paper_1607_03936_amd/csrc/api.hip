@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "solver.h"
 
@@ -53,6 +54,29 @@ Mesh make_mesh(int N, int k) {
   m.np = modes(k, nullptr, nullptr, nullptr);
   m.h = 1.0 / N;
   return m;
+}
+
+// Fixed device workspace of wb_apply_A_noalloc: each device that runs it holds its own copy
+// until the process ends; host code uses only the address taken with hipGetSymbolAddress.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64u << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The scratch array's device address on the current device (looked up once per device).
+void* noalloc_scratch() {
+  int dev = 0;
+  WB_HIP(hipGetDevice(&dev));
+  WB_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, WB_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    WB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    WB_REQUIRE(ptr != nullptr, WB_EHIP, "hipGetSymbolAddress returned no address");
+    scratch_ptr[dev] = ptr;
+  }
+  return scratch_ptr[dev];
 }
 
 // Face-array workspace of the scatter operators for standalone applies on this mesh
@@ -234,6 +258,28 @@ wb_status wb_apply_A(const wb_mesh* mh, const wb_visc* v, const double* u, doubl
     const Mesh& m = mh->m;
     launch_op<double>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q, nullptr, nullptr, nullptr,
                       false, mesh_work(mh));
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_A_noalloc(const wb_mesh* mh, const wb_visc* v, const double* u, double* y,
+                             void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && v && u && y, WB_EINVAL, "NULL argument");
+    WB_REQUIRE(u != y, WB_EINVAL, "in-place apply is not allowed");
+    const Mesh& m = mh->m;
+    const size_t need = op_workspace_bytes_capped(3, m.N, m.k, sizeof(double), NOALLOC_SCRATCH_BYTES);
+    if (need > NOALLOC_SCRATCH_BYTES) {
+      char msg[160];
+      snprintf(msg, sizeof(msg), "wb_apply_A_noalloc: this mesh needs %zu bytes of workspace, above "
+               "the fixed %zu", need, NOALLOC_SCRATCH_BYTES);
+      throw Error{WB_EINVAL, msg};
+    }
+    void* work = noalloc_scratch();
+    WorkspaceCap cap(NOALLOC_SCRATCH_BYTES);
+    launch_op<double>(S(stream), F_A | F_DIR, 3, m.N, m.k, u, y, v->mu_q, nullptr, nullptr, nullptr,
+                      false, work);
     check_launch();
     return WB_OK;
   });

@@ -33,6 +33,18 @@ enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8, F_MF = 16, F_MF3 = 32 };
 // matrix instead: B one element x-line per lane, B^T one node line segment per thread, one
 // kernel each and no workspace.
 size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size);
+// Workspace the operator needs in the form it takes when the two-pass element buffer may use at
+// most `cap` bytes (the brick form otherwise).
+size_t op_workspace_bytes_capped(int NC, int N, int k, size_t elem_size, size_t cap);
+// While alive, operator launches of this thread use the two-pass form only if its element buffer
+// takes at most `bytes` (for callers that bring a fixed workspace).
+struct WorkspaceCap {
+  explicit WorkspaceCap(size_t bytes);
+  ~WorkspaceCap();
+  WorkspaceCap(const WorkspaceCap&) = delete;
+  WorkspaceCap& operator=(const WorkspaceCap&) = delete;
+  size_t prev;
+};
 // Process-wide size limit (MB of FP64 element contributions, clamped to [0, 128]) below which A
 // applies use the two-pass form; returns the previous limit.
 double set_two_pass_limit(double mb);

@@ -746,8 +746,12 @@ std::atomic<int> matrix_core_ops{1};
 inline size_t elem_buf_bytes(int NC, int N, int k) {
   return sizeof(double) * NC * (size_t)N * N * N * (size_t)(k + 1) * (k + 1) * (k + 1);
 }
+// Per-thread cap on the two-pass element buffer (the caller's workspace size; unlimited by
+// default), set for the duration of a call by WorkspaceCap.
+thread_local size_t two_pass_cap = ~(size_t)0;
 inline bool two_pass(int NC, int N, int k) {
-  return elem_buf_bytes(NC, N, k) <= two_pass_limit.load(std::memory_order_relaxed);
+  const size_t b = elem_buf_bytes(NC, N, k);
+  return b <= two_pass_limit.load(std::memory_order_relaxed) && b <= two_pass_cap;
 }
 
 inline BrickGeom brick_geom(int N, int k, int BX, int BY) {
@@ -2993,6 +2997,26 @@ double set_two_pass_limit(double mb) {
   two_pass_limit.store((size_t)b);
   return prev;
 }
+
+size_t op_workspace_bytes_capped(int NC, int N, int k, size_t elem_size, size_t cap) {
+  int BX = 8, BY = 8;
+  switch (k + 1) {
+    case 2: BX = Tile<2>::BX; BY = Tile<2>::BY; break;
+    case 3: BX = Tile<3>::BX; BY = Tile<3>::BY; break;
+    case 4: BX = Tile<4>::BX; BY = Tile<4>::BY; break;
+    case 5: BX = Tile<5>::BX; BY = Tile<5>::BY; break;
+    case 6: BX = Tile<6>::BX; BY = Tile<6>::BY; break;
+    default: break;
+  }
+  const size_t b = elem_buf_bytes(NC, N, k);
+  if (b <= two_pass_limit.load(std::memory_order_relaxed) && b <= cap)
+    return b / sizeof(double) * elem_size;
+  const BrickGeom G = brick_geom(N, k, BX, BY);
+  return elem_size * NC * std::max<size_t>(G.per_comp, 1);
+}
+
+WorkspaceCap::WorkspaceCap(size_t bytes) : prev(two_pass_cap) { two_pass_cap = bytes; }
+WorkspaceCap::~WorkspaceCap() { two_pass_cap = prev; }
 
 size_t op_workspace_bytes(int NC, int N, int k, size_t elem_size) {
   const size_t elem_buf = elem_buf_bytes(NC, N, k) <= TWO_PASS_MAX_BYTES

@@ -83,6 +83,7 @@ SIGNATURES = {
     "wb_visc_destroy": (None, [VP]),
     "wb_rhs_sinker": (I, [VP, VP, I, D, D, D, VP, VP]),
     "wb_apply_A": (I, [VP, VP, VP, VP, VP]),
+    "wb_apply_A_noalloc": (I, [VP, VP, VP, VP, VP]),
     "wb_apply_B": (I, [VP, VP, VP, VP]),
     "wb_apply_BT": (I, [VP, VP, VP, VP]),
     "wb_apply_A_add": (I, [VP, VP, VP, VP, VP]),
@@ -272,6 +273,12 @@ def wb_apply_A_lowp(mesh, visc, prec, u, y, stream=None):
     import torch
     _check(lib().wb_apply_A_lowp(mesh.h, visc.h, prec, _ptr(u, torch.float32, mesh.u_len),
                                  _ptr(y, torch.float32, mesh.u_len), _stream(stream)))
+
+
+def wb_apply_A_noalloc(mesh, visc, u, y, stream=None):
+    import torch
+    _check(lib().wb_apply_A_noalloc(mesh.h, visc.h, _ptr(u, torch.float64, mesh.u_len),
+                                    _ptr(y, torch.float64, mesh.u_len), _stream(stream)))
 
 
 def wb_apply_B(mesh, u, p, stream=None):
