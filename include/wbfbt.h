@@ -186,6 +186,12 @@ WB_API wb_status wb_apply_stokes(const wb_mesh* m, const wb_visc* v, const doubl
  * WB_BF16X1 (BF16 MFMA contractions accumulated in FP32, see wb_prec). */
 WB_API wb_status wb_apply_A_lowp(const wb_mesh* m, const wb_visc* v, int prec, const float* u,
                                  float* y, void* stream);
+/* Reduced-precision divergence and gradient (the B and B^T of wb_apply_B / wb_apply_BT on FP32
+ * buffers, used by the precision forms of the preconditioner): prec = WB_FP32 (FP32 arithmetic,
+ * the uniform mesh's tensor-product line kernels), WB_BF16 or WB_BF16X1 (the sum-factorized
+ * element contractions on the BF16 matrix cores, FP32 accumulation; k <= 4).  k >= 2. */
+WB_API wb_status wb_apply_B_lowp(const wb_mesh* m, int prec, const float* u, float* p, void* stream);
+WB_API wb_status wb_apply_BT_lowp(const wb_mesh* m, int prec, const float* p, float* u, void* stream);
 
 /* ---- solver: w-BFBT (eq. 8, Sec. 5) + p/h-multigrid (Sec. 6) + FGMRES (eq. 3) ----
  * Builds the velocity multigrid hierarchy, the weights C = M(w_l), D = M(w_r),

@@ -345,6 +345,40 @@ wb_status wb_apply_A_lowp(const wb_mesh* mh, const wb_visc* vc, int prec, const 
   });
 }
 
+namespace {
+int lowp_flag(int prec, int k) {
+  WB_REQUIRE(prec == WB_FP32 || prec == WB_BF16 || prec == WB_BF16X1, WB_EINVAL,
+             "prec must be WB_FP32, WB_BF16 or WB_BF16X1");
+  WB_REQUIRE(k >= 2, WB_EUNSUPPORTED, "B and B^T need k >= 2");
+  WB_REQUIRE(prec == WB_FP32 || k <= 4, WB_EUNSUPPORTED, "the BF16 forms are built for k <= 4");
+  return prec == WB_BF16 ? F_MF3 : (prec == WB_BF16X1 ? F_MF : 0);
+}
+}  // namespace
+
+wb_status wb_apply_B_lowp(const wb_mesh* mh, int prec, const float* u, float* p, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && u && p, WB_EINVAL, "NULL argument");
+    const Mesh& m = mh->m;
+    const int mf = lowp_flag(prec, m.k);
+    launch_op<float>(S(stream), F_B | F_DIR | mf, 3, m.N, m.k, u, nullptr, nullptr, nullptr, p,
+                     nullptr, false, nullptr);
+    check_launch();
+    return WB_OK;
+  });
+}
+
+wb_status wb_apply_BT_lowp(const wb_mesh* mh, int prec, const float* p, float* u, void* stream) {
+  return guard([&] {
+    WB_REQUIRE(mh && u && p, WB_EINVAL, "NULL argument");
+    const Mesh& m = mh->m;
+    const int mf = lowp_flag(prec, m.k);
+    launch_op<float>(S(stream), F_BT | F_DIR | mf, 3, m.N, m.k, nullptr, u, nullptr, p, nullptr,
+                     nullptr, false, mesh_work(mh));
+    check_launch();
+    return WB_OK;
+  });
+}
+
 wb_status wb_solver_create(const wb_mesh* mh, const wb_visc* v, const wb_opts* opts, void* stream,
                            wb_solver** out) {
   return guard([&] {

@@ -740,8 +740,9 @@ struct BrickGeom {
 // cap, so the limit may change while solvers exist.
 constexpr size_t TWO_PASS_MAX_BYTES = 128u << 20;
 std::atomic<size_t> two_pass_limit{TWO_PASS_MAX_BYTES};
-// FP64 order-3 brick applies of A and the Poisson operator on the matrix cores (k_op_mfma) or with
-// line contractions in LDS (k_op_brick).
+// Order-3 brick applies of A and the Poisson operator (FP64, and the FP32 data of the FP32
+// precision form) on the FP64 matrix cores (k_op_mfma), or with line contractions in LDS
+// (k_op_brick).
 std::atomic<int> matrix_core_ops{1};
 inline size_t elem_buf_bytes(int NC, int N, int k) {
   return sizeof(double) * NC * (size_t)N * N * N * (size_t)(k + 1) * (k + 1) * (k + 1);
@@ -1128,12 +1129,14 @@ __device__ __forceinline__ double from_left(double v) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int NC, int F, int EP>
+// T is the storage type of the vectors, the coefficient and the face array (FP64, or FP32 for the
+// FP32 precision form); the arithmetic is FP64 throughout (matrix cores and registers).
+template <int NC, typename T, int F, int EP>
 __global__ void __launch_bounds__(MF_NT, 2)
-k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
-          double* __restrict__ y, const double* __restrict__ coef,
-          const double* __restrict__ sin_, double* __restrict__ face, const int add,
-          const Epi<double> ep) {
+k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
+          T* __restrict__ y, const T* __restrict__ coef,
+          const T* __restrict__ sin_, T* __restrict__ face, const int add,
+          const Epi<T> ep) {
   static_assert(Tile<4>::BX == MF_BX && Tile<4>::BY == MF_BY, "brick tile of order 3");
   constexpr int k = 3, YW = MfLds<NC>::YW, XW = MfLds<NC>::XW, XOFF = MfLds<NC>::XOFF;
   constexpr int BUF = MfLds<NC>::BUF;
@@ -1147,8 +1150,8 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
   // contiguous run of tiles, and the cache lines that neighbouring tiles share stay in one L2.
   int tx, ty, bz;
   {
-    const int T = G.nbx * G.nby * G.nbz, id = blockIdx.x, r = id & 7;
-    const int L = r * (T >> 3) + min(r, T & 7) + (id >> 3);
+    const int nt = G.nbx * G.nby * G.nbz, id = blockIdx.x, r = id & 7;
+    const int L = r * (nt >> 3) + min(r, nt & 7) + (id >> 3);
     tx = L % G.nbx;
     ty = (L / G.nbx) % G.nby;
     bz = L / (G.nbx * G.nby);
@@ -1204,11 +1207,13 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
     }
   }
   const int colg = gi + M * gj;
-  auto store = [&](const double (&val)[NC], int gz, bool general) {
+  auto store = [&](const double (&vd)[NC], int gz, bool general) {
+    T val[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) val[c] = (T)vd[c];
     if (general) {
       if (owner)
-        store_node<4, NC, double, DIR, EP>(G, gi, gj, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add,
-                                           ep);
+        store_node<4, NC, T, DIR, EP>(G, gi, gj, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
     } else if (kind == K_NODE) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
@@ -1219,7 +1224,7 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
     } else if (kind == K_ZERO) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        emit<EP>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, 0.0, y, add);
+        emit<EP>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, T(0), y, add);
     }
   };
   // sums the np planes of v across the tile (v holds this lane's element contributions) and stores
@@ -1287,8 +1292,8 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
   // masked afterwards (Dirichlet nodes and idle lanes: 0)
   auto raw_node = [&](int c, int gl) -> double {
     const size_t j = (size_t)c * nn + (size_t)col + (size_t)M * M * gl;
-    if constexpr (EP == EPI_CHEB_ZERO) return ep.gamma * ep.dinv[j] * ep.b[j];
-    else return u[j];
+    if constexpr (EP == EPI_CHEB_ZERO) return (double)(ep.gamma * ep.dinv[j] * ep.b[j]);
+    else return (double)u[j];
   };
   auto live_node = [&](int gl) -> bool { return valid && !(DIR && (bij || gl == 0 || gl == M - 1)); };
   double cq[4];             // coefficient of the current layer at the lane's Gauss points
@@ -1300,7 +1305,7 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
   auto load_layer = [&](int ez, LBuf& b) {
     const size_t eb = (size_t)(valid ? ex + N * (ey + N * ez) : 0) * 64 + f0 + 4 * f2;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) b.c[r] = coef[eb + 16 * r];
+    for (int r = 0; r < 4; ++r) b.c[r] = (double)coef[eb + 16 * r];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -1312,7 +1317,7 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
 #pragma unroll
     for (int r = 1; r < 4; ++r) {
       const int gl = ez * k + r;
-      const double sc = sin_ != nullptr ? sin_[(size_t)col + (size_t)M * M * gl] : 1.0;
+      const double sc = sin_ != nullptr ? (double)sin_[(size_t)col + (size_t)M * M * gl] : 1.0;
       const bool lv = live_node(gl);
 #pragma unroll
       for (int c = 0; c < NC; ++c) uc[c][r] = lv ? b.u[c][r - 1] * sc : 0.0;
@@ -1320,7 +1325,7 @@ k_op_mfma(const BrickDev G, const double hh, const double* __restrict__ u,
   };
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const double sc = sin_ != nullptr ? sin_[(size_t)col + (size_t)M * M * Z0] : 1.0;
+    const double sc = sin_ != nullptr ? (double)sin_[(size_t)col + (size_t)M * M * Z0] : 1.0;
     uc[c][0] = live_node(Z0) ? raw_node(c, Z0) * sc : 0.0;
   }
   LBuf lb0, lb1;
@@ -1802,10 +1807,10 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
     {
       ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
       bool done = false;
-      if constexpr (n == 4 && sizeof(T) == 8 && MF == 0 && (F & (F_BT | F_B)) == 0) {
+      if constexpr (n == 4 && MF == 0 && (F & (F_BT | F_B)) == 0) {
         if (matrix_core_ops.load(std::memory_order_relaxed)) {
-          hipLaunchKernelGGL((k_op_mfma<NC, F, EP>), dim3(G.nbx * G.nby * G.nbz), dim3(MF_NT), 0, st,
-                             D, (double)hh, u, y, coef, sin, face, (int)add, ep);
+          hipLaunchKernelGGL((k_op_mfma<NC, T, F, EP>), dim3(G.nbx * G.nby * G.nbz), dim3(MF_NT), 0,
+                             st, D, (double)hh, u, y, coef, sin, face, (int)add, ep);
           done = true;
         }
       }

@@ -85,6 +85,8 @@ SIGNATURES = {
     "wb_apply_A": (I, [VP, VP, VP, VP, VP]),
     "wb_apply_A_noalloc": (I, [VP, VP, VP, VP, VP]),
     "wb_apply_B": (I, [VP, VP, VP, VP]),
+    "wb_apply_B_lowp": (I, [VP, I, VP, VP, VP]),
+    "wb_apply_BT_lowp": (I, [VP, I, VP, VP, VP]),
     "wb_apply_BT": (I, [VP, VP, VP, VP]),
     "wb_apply_A_add": (I, [VP, VP, VP, VP, VP]),
     "wb_apply_stokes": (I, [VP, VP, VP, VP, VP, VP, VP]),
@@ -285,6 +287,18 @@ def wb_apply_B(mesh, u, p, stream=None):
     import torch
     _check(lib().wb_apply_B(mesh.h, _ptr(u, torch.float64, mesh.u_len),
                             _ptr(p, torch.float64, mesh.p_len), _stream(stream)))
+
+
+def wb_apply_B_lowp(mesh, prec, u, p, stream=None):
+    import torch
+    _check(lib().wb_apply_B_lowp(mesh.h, prec, _ptr(u, torch.float32, mesh.u_len),
+                                 _ptr(p, torch.float32, mesh.p_len), _stream(stream)))
+
+
+def wb_apply_BT_lowp(mesh, prec, p, u, stream=None):
+    import torch
+    _check(lib().wb_apply_BT_lowp(mesh.h, prec, _ptr(p, torch.float32, mesh.p_len),
+                                  _ptr(u, torch.float32, mesh.u_len), _stream(stream)))
 
 
 def wb_apply_BT(mesh, p, u, stream=None):

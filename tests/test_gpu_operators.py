@@ -301,3 +301,74 @@ def test_apply_A_q3_matrix_core_form_matches_assembled(N):
     finally:
         wb.wb_set_two_pass_limit(prev_limit)
         wb.wb_set_matrix_core_ops(prev_mc)
+
+
+@pytest.mark.parametrize("N", [4, 11])
+def test_apply_A_q3_fp32_storage_forms(N):
+    # the FP32 precision form at order 3 above the two-pass size: FP32 vectors and coefficient in
+    # memory, FP64 arithmetic on the matrix cores (or FP32 line contractions in LDS with the
+    # matrix cores switched off).  Both round to FP32 (relative error 1e-9 .. 1e-5 against the
+    # assembled FP64 oracle); the matrix-core form only rounds its inputs and outputs, so it
+    # lands closer than the FP32-arithmetic line form.
+    wb = _wb()
+    om = fem.Mesh(N, 3)
+    rng = np.random.default_rng(40 + N)
+    mu_q = 10.0 ** rng.uniform(-4, 4, (om.E, om.n ** 3))
+    m = wb.Mesh(N, 3)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(np.ones(om.n_nodes)))
+    u = random_vector(14, om.u_dof)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0.0
+    want = fem.assemble_A(om, mu_q) @ ui
+    want[om.vel_boundary] = 0.0
+    prev_limit = wb.wb_set_two_pass_limit(0.0)
+    prev_mc = wb.wb_set_matrix_core_ops(True)
+    errs = {}
+    try:
+        for on in (True, False):
+            wb.wb_set_matrix_core_ops(on)
+            y = torch.empty(m.u_len, dtype=torch.float32, device="cuda")
+            wb.wb_apply_A_lowp(m, v, wb.WB_FP32, dev(u).float(), y)
+            got = host(y).astype(np.float64)
+            errs[on] = _rel(got, want)
+            assert np.all(got[om.vel_boundary] == 0.0)
+            if on:
+                y2 = torch.empty_like(y)
+                wb.wb_apply_A_lowp(m, v, wb.WB_FP32, dev(u).float(), y2)
+                assert torch.equal(y, y2)
+    finally:
+        wb.wb_set_two_pass_limit(prev_limit)
+        wb.wb_set_matrix_core_ops(prev_mc)
+    print(f"FP32 A N={N} k=3: matrix cores {errs[True]:.2e}, LDS lines {errs[False]:.2e}")
+    assert 1e-9 < errs[True] < 1e-5 and 1e-9 < errs[False] < 1e-5
+    assert errs[True] <= errs[False]
+
+
+@pytest.mark.parametrize("N,k", [c for c in BF16_CASES if c[1] >= 2])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16x1"])
+def test_apply_B_BT_low_precision(N, k, form):
+    """Reduced-precision divergence and gradient against the assembled oracle.  FP32: FP32 rounding
+    (relative error 1e-9 .. 1e-5).  BF16 on the matrix cores: three contractions per value,
+    bf16x3 about 2^-16 each, bf16x1 about 2^-8 each, both above the FP32 level."""
+    wb = _wb()
+    om = fem.Mesh(N, k)
+    m = wb.Mesh(N, k)
+    B = fem.assemble_B(om)
+    u = random_vector(51, om.u_dof)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0.0
+    p = random_vector(52, om.p_dof)
+    prec = {"fp32": wb.WB_FP32, "bf16x3": wb.WB_BF16, "bf16x1": wb.WB_BF16X1}[form]
+    pg = torch.empty(m.p_len, dtype=torch.float32, device="cuda")
+    wb.wb_apply_B_lowp(m, prec, dev(u).float(), pg)
+    ug = torch.empty(m.u_len, dtype=torch.float32, device="cuda")
+    wb.wb_apply_BT_lowp(m, prec, dev(p).float(), ug)
+    want_p = B @ ui
+    want_u = B.T @ p
+    want_u[om.vel_boundary] = 0.0
+    ep = np.linalg.norm(host(pg).astype(np.float64) - want_p) / np.linalg.norm(want_p)
+    eu = np.linalg.norm(host(ug).astype(np.float64) - want_u) / np.linalg.norm(want_u)
+    print(f"{form} N={N} k={k}: B {ep:.2e}, B^T {eu:.2e}")
+    assert np.all(host(ug)[om.vel_boundary] == 0.0)
+    lo, hi = {"fp32": (1e-10, 1e-5), "bf16x3": (3e-8, 2e-4), "bf16x1": (1e-4, 2.5e-2)}[form]
+    assert lo < ep < hi and lo < eu < hi

@@ -241,11 +241,23 @@ def test_brick_form_preconditioner_matches_oracle(name, mc):
         wb.wb_set_matrix_core_ops(prev_mc)
 
 
-@pytest.mark.parametrize("name", ["n8k2", "n4k5"])
-def test_mixed_precision_preconditioner_reaches_tolerance(name):
+@pytest.mark.parametrize("name,brick", [("n8k2", False), ("n4k5", False), ("n4k3", True)])
+def test_mixed_precision_preconditioner_reaches_tolerance(name, brick):
+    # brick: order-3 applies in the brick form (FP32 storage, FP64 matrix-core arithmetic)
     wb = _wb()
     w, st, P, m, v, s = _pair(name)
     om = st.mesh
+    if not brick:
+        _mixed_precision_solve(wb, w, om, m, v, s)
+        return
+    prev = wb.wb_set_two_pass_limit(0.0)
+    try:
+        _mixed_precision_solve(wb, w, om, m, v, wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r))
+    finally:
+        wb.wb_set_two_pass_limit(prev)
+
+
+def _mixed_precision_solve(wb, w, om, m, v, s):
     f = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
     wb.wb_rhs_sinker(m, w.centers(), w.delta, w.omega, w.beta, f)
     u64 = torch.empty(om.u_dof, dtype=torch.float64, device="cuda")
