@@ -1130,7 +1130,10 @@ __device__ __forceinline__ double from_left(double v) {
 }
 
 // T is the storage type of the vectors, the coefficient and the face array (FP64, or FP32 for the
-// FP32 precision form); the arithmetic is FP64 throughout (matrix cores and registers).
+// FP32 precision form); the arithmetic is FP64 throughout (matrix cores and registers).  EP is an
+// output epilogue, or EPI_ZERO_IN: plain stores of the operator applied to d0 = gamma D^-1 b,
+// formed as it is read (the operator half of EPI_CHEB_ZERO, whose epilogue then runs apart).
+constexpr int EPI_ZERO_IN = 5;
 template <int NC, typename T, int F, int EP>
 __global__ void __launch_bounds__(MF_NT, 2)
 k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
@@ -1141,6 +1144,7 @@ k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
   constexpr int k = 3, YW = MfLds<NC>::YW, XW = MfLds<NC>::XW, XOFF = MfLds<NC>::XOFF;
   constexpr int BUF = MfLds<NC>::BUF;
   constexpr bool DIR = (F & F_DIR) != 0;
+  constexpr int EO = EP == EPI_ZERO_IN ? EPI_STORE : EP;   // output epilogue
   __shared__ double ybuf[2 * BUF];
   const int N = G.N, M = G.M, nn = G.nn;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, px = wave % MF_PX, ly = wave / MF_PX;
@@ -1213,18 +1217,18 @@ k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
     for (int c = 0; c < NC; ++c) val[c] = (T)vd[c];
     if (general) {
       if (owner)
-        store_node<4, NC, T, DIR, EP>(G, gi, gj, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
+        store_node<4, NC, T, DIR, EO>(G, gi, gj, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
     } else if (kind == K_NODE) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        emit<EP>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, val[c], y, add);
+        emit<EO>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, val[c], y, add);
     } else if (kind == K_FACE) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) face[(size_t)c * G.per_comp + base + (size_t)M * gz] = val[c];
     } else if (kind == K_ZERO) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        emit<EP>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, T(0), y, add);
+        emit<EO>(ep, (size_t)c * nn + (size_t)colg + (size_t)M * M * gz, T(0), y, add);
     }
   };
   // sums the np planes of v across the tile (v holds this lane's element contributions) and stores
@@ -1292,8 +1296,10 @@ k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
   // masked afterwards (Dirichlet nodes and idle lanes: 0)
   auto raw_node = [&](int c, int gl) -> double {
     const size_t j = (size_t)c * nn + (size_t)col + (size_t)M * M * gl;
-    if constexpr (EP == EPI_CHEB_ZERO) return (double)(ep.gamma * ep.dinv[j] * ep.b[j]);
-    else return (double)u[j];
+    if constexpr (EP == EPI_CHEB_ZERO || EP == EPI_ZERO_IN)
+      return (double)(ep.gamma * ep.dinv[j] * ep.b[j]);
+    else
+      return (double)u[j];
   };
   auto live_node = [&](int gl) -> bool { return valid && !(DIR && (bij || gl == 0 || gl == M - 1)); };
   double cq[4];             // coefficient of the current layer at the lane's Gauss points
@@ -1734,6 +1740,23 @@ __global__ void k_face_sum(const BrickDev G, const T* __restrict__ face, T* __re
   for (int c = 0; c < NC; ++c) emit<EP>(ep, (size_t)c * G.nn + g, val[c], y, add);
 }
 
+// The epilogue of an operator apply as a pass of its own: t holds the operator's output, and
+// t is the buffer the epilogue overwrites only after reading it at the same index (r for the
+// residual, the new search direction otherwise), so t carries no restrict qualifier.
+template <typename T, int EP>
+__global__ void __launch_bounds__(256) k_epi_apply(const size_t n, const T* t, const Epi<T> ep) {
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    const T v = t[j];
+    emit<EP>(ep, j, v, static_cast<T*>(nullptr), 0);
+  }
+}
+
+template <int EP, typename T>
+T* epi_target(const Epi<T>& ep) {
+  return EP == EPI_RESID ? ep.r : ep.dnew;
+}
+
 struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t st;
@@ -1809,9 +1832,28 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
       bool done = false;
       if constexpr (n == 4 && MF == 0 && (F & (F_BT | F_B)) == 0) {
         if (matrix_core_ops.load(std::memory_order_relaxed)) {
-          hipLaunchKernelGGL((k_op_mfma<NC, T, F, EP>), dim3(G.nbx * G.nby * G.nbz), dim3(MF_NT), 0,
-                             st, D, (double)hh, u, y, coef, sin, face, (int)add, ep);
-          done = true;
+          if constexpr (EP == EPI_STORE) {
+            hipLaunchKernelGGL((k_op_mfma<NC, T, F, EPI_STORE>), dim3(G.nbx * G.nby * G.nbz),
+                               dim3(MF_NT), 0, st, D, (double)hh, u, y, coef, sin, face, (int)add,
+                               ep);
+            done = true;
+          } else {
+            // The epilogue runs as a separate streaming pass: fused into this kernel, its loads
+            // wait behind the layer prefetch and stall every layer.  The operator output goes
+            // to the buffer the epilogue overwrites last (bit-identical results).
+            constexpr int EK = EP == EPI_CHEB_ZERO ? EPI_ZERO_IN : EPI_STORE;
+            T* t = epi_target<EP>(ep);
+            hipLaunchKernelGGL((k_op_mfma<NC, T, F, EK>), dim3(G.nbx * G.nby * G.nbz),
+                               dim3(MF_NT), 0, st, D, (double)hh, u, t, coef, sin, face, 0, ep);
+            const size_t tot = (size_t)(G.nbx + G.nby + G.nbz - 3) * G.plane;
+            if (tot > 0)
+              hipLaunchKernelGGL((k_face_sum<n, NC, T, (F & F_DIR) != 0, EPI_STORE>),
+                                 dim3(grid_for(tot, 256)), dim3(256), 0, st, D, face, t, 0, ep);
+            const size_t len = (size_t)NC * nn;
+            hipLaunchKernelGGL((k_epi_apply<T, EP>), dim3(grid_for(len, 256)), dim3(256), 0, st,
+                               len, (const T*)t, ep);
+            return;
+          }
         }
       }
       if (!done)
