@@ -336,8 +336,9 @@ WB_API void wb_profile_enable(int on);
 WB_API long long wb_profile_summary(char* buf, long long len, int reset);
 
 /* ---- operator form ----
- * A and Poisson applies whose element contributions take at most `mb` MB in FP64 (clamped to
- * [0, 128]; 128 by default) run in two passes (all elements into an element buffer, then per-node
+ * A and Poisson applies whose element contributions take at most `mb` MB (10^6 bytes) in FP64
+ * (clamped to [0, 134.2], i.e. 128 MiB; 96 MiB = 100.7 MB by default) run in two passes (all
+ * elements into an element buffer, then per-node
  * sums); larger ones as brick scatters with brick-face sums.  Both give the operator up to
  * rounding order.  Process-wide, for tests and tuning; workspaces are sized for both forms, so it
  * may be changed at any time (a captured preconditioner graph keeps the form it was captured

@@ -25,7 +25,8 @@ enum : int { F_A = 1, F_BT = 2, F_B = 4, F_DIR = 8, F_MF = 16, F_MF3 = 32 };
 //   sin: optional per-node input scaling.
 // Operators that scatter to nodes (A, the fused Stokes operator) run in two kernels, with `work`
 // at least op_workspace_bytes(NC, N, k, sizeof(double)) bytes (valid for FP32 data as well):
-//  - A alone while its element contributions fit in 128 MB (FP64): all elements in parallel into
+//  - A alone while its element contributions fit in the two-pass limit (96 MiB of FP64 by
+//    default, at most 128 MiB): all elements in parallel into
 //    an element buffer in `work`, then per-node sums of the at most eight contributions;
 //  - otherwise, and for the fused Stokes operator: blocks own bricks of elements and accumulate
 //    in LDS; values on internal brick faces pass through `work` and are summed by a second kernel.
@@ -45,8 +46,8 @@ struct WorkspaceCap {
   WorkspaceCap& operator=(const WorkspaceCap&) = delete;
   size_t prev;
 };
-// Process-wide size limit (MB of FP64 element contributions, clamped to [0, 128]) below which A
-// applies use the two-pass form; returns the previous limit.
+// Process-wide size limit (MB = 10^6 bytes of FP64 element contributions, clamped to 128 MiB; 96
+// MiB by default) below which A applies use the two-pass form; returns the previous limit.
 double set_two_pass_limit(double mb);
 // FP64 order-3 applies of A and the Poisson operator above the two-pass size: on the FP64 matrix
 // cores (on != 0, the default) or with line contractions staged in LDS; returns the previous setting.
@@ -249,6 +250,11 @@ void launch_mdot(hipStream_t st, size_t n, int nv, const double* V, size_t ld, c
                  double* partial, double* h);
 void launch_gemv_sub(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* h,
                      double* w);
+// w -= sum_v h[v] V[v], then h2[v] = V[v] . w for the updated w, from one read of V (the update of
+// one classical Gram-Schmidt sweep and the projections of the next); false (nothing launched) when
+// nv exceeds the kernel's LDS staging.
+bool launch_gs_sub_dot(hipStream_t st, size_t n, int nv, const double* V, size_t ld,
+                       const double* h, double* w, double* partial, double* h2);
 void launch_gemv_add(hipStream_t st, size_t n, int nv, const double* Z, size_t ld, const double* y,
                      double* x);
 

@@ -8,7 +8,7 @@
 // n^2 threads per element, each holding a z-column in registers; x and y
 // contractions exchange through LDS.  The divergence and the gradient alone
 // use the precomputed tensor-product element matrix of the uniform mesh
-// (k_div_line, k_grad_line).
+// (k_div_elem, k_grad_line).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -118,6 +118,15 @@ __device__ inline void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); 
 __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
 inline unsigned grid_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// XCD-aware block order: workgroups are dealt round-robin to the eight XCDs (id % 8), so block id
+// takes the work item (start of its XCD's range) + id / 8; each XCD then owns a contiguous run of
+// work items, and the cache lines that neighbouring items share stay in one L2.  A bijection of
+// [0, nb).
+__device__ __forceinline__ int xcd_order(const int id, const int nb) {
+  const int r = id & 7;
+  return r * (nb >> 3) + min(r, nb & 7) + (id >> 3);
+}
 
 // ------------------------------------------------------------------ operator
 // All threads of one element live in one wavefront, so the exchanges inside an element need
@@ -734,12 +743,14 @@ struct BrickGeom {
 };
 
 // The two-pass form (k_op_elem + k_node_sum) is used while the element contributions take at
-// most two_pass_limit bytes in FP64 (at most TWO_PASS_MAX_BYTES, the default); larger problems use
-// the brick scatter (no element buffer in HBM).  The choice does not depend on the data type, so
-// a workspace sized for FP64 serves FP32 too, and workspaces are sized for both forms up to the
-// cap, so the limit may change while solvers exist.
+// most two_pass_limit bytes in FP64 (at most TWO_PASS_MAX_BYTES; 96 MiB by default); larger
+// problems use the brick scatter (no element buffer in HBM).  The choice does not depend on the
+// data type, so a workspace sized for FP64 serves FP32 too, and workspaces are sized for both
+// forms up to TWO_PASS_MAX_BYTES, so the limit may change while solvers exist.  With the 96 MiB
+// default the order-3 Poisson operator on 64^3 elements (a 128 MiB buffer) takes the matrix-core
+// brick form, about 10 ms faster per 64^3 Q3 solve than the two-pass form.
 constexpr size_t TWO_PASS_MAX_BYTES = 128u << 20;
-std::atomic<size_t> two_pass_limit{TWO_PASS_MAX_BYTES};
+std::atomic<size_t> two_pass_limit{96u << 20};
 // Order-3 brick applies of A and the Poisson operator (FP64, and the FP32 data of the FP32
 // precision form) on the FP64 matrix cores (k_op_mfma), or with line contractions in LDS
 // (k_op_brick).
@@ -851,7 +862,7 @@ struct WinPad {
 
 // Divergence only (no scatter) with the sum-factorized element machinery, element-parallel; the
 // pressure modes go through the epilogue.  Used by the BF16 forms (their contractions on the
-// matrix cores); the other forms use k_div_line.
+// matrix cores); the other forms use k_div_elem.
 template <int n, typename T, int F, int MF, int EP>
 __global__ void __launch_bounds__(256)
 k_op_gather(const int N, const int k, const int M, const int E, const int nn, const T hh,
@@ -1149,13 +1160,10 @@ k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
   const int N = G.N, M = G.M, nn = G.nn;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, px = wave % MF_PX, ly = wave / MF_PX;
   const int f0 = lane & 3, f1 = (lane >> 2) & 3, f2 = lane >> 4;
-  // XCD-aware tile order: workgroups go round-robin to the eight XCDs, so workgroup id maps to
-  // the tile L = (start of its XCD's range) + (id / 8) in x-fastest order; each XCD then owns a
-  // contiguous run of tiles, and the cache lines that neighbouring tiles share stay in one L2.
+  // XCD-aware tile order (tiles numbered x fastest)
   int tx, ty, bz;
   {
-    const int nt = G.nbx * G.nby * G.nbz, id = blockIdx.x, r = id & 7;
-    const int L = r * (nt >> 3) + min(r, nt & 7) + (id >> 3);
+    const int L = xcd_order(blockIdx.x, G.nbx * G.nby * G.nbz);
     tx = L % G.nbx;
     ty = (L / G.nbx) % G.nby;
     bz = L / (G.nbx * G.nby);
@@ -1537,7 +1545,7 @@ __global__ void __launch_bounds__(256)
 k_grad_line(const int N, const int M, const int nn, const T hh, const T* __restrict__ p,
             T* __restrict__ y, const int add) {
   constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= N * M * M) return;
   const int ex = t % N, gy = (t / N) % M, gz = t / (N * M);
   T v[k][3];
@@ -1605,32 +1613,37 @@ k_grad_line(const int N, const int M, const int nn, const T hh, const T* __restr
   }
 }
 
-// Divergence with the Dirichlet mask (and an optional per-node input scaling), one lane per
-// element x-line: lane r of element e takes the nodes (i, j = r % n, l = r / n), i = 0..k,
-// contracts them in x into R_c[a] and multiplies by its y and z weights into a partial of every
-// mode; the n^2 partials of each mode are summed in LDS in lane order and go out through the
-// epilogue (pressure outputs e n_p + m).
+// Divergence with the Dirichlet mask (and an optional per-node input scaling).  A block holds n
+// wavefronts on the same 64 consecutive elements (lane = element, consecutive in x, so each load
+// instruction covers a contiguous run of nodes and the n loads of a node line reuse its cache
+// lines); wavefront l takes the node lines (j, l), j = 0..k, of its element: it contracts each
+// line's nodes in x into R_c[a] and adds the line's share of every mode.  The n partial sums of
+// an element are added in LDS in the order l = 0..k and go out through the epilogue (pressure
+// outputs e n_p + m).
 template <int n, typename T, int EP>
-__global__ void __launch_bounds__(256)
-k_div_line(const int N, const int M, const int E, const int nn, const T hh,
+__global__ void __launch_bounds__(64 * n)
+k_div_elem(const int N, const int M, const int E, const int nn, const T hh,
            const T* __restrict__ u, const T* __restrict__ sin_, T* __restrict__ pout,
            const int add, const Epi<T> ep) {
-  constexpr int k = n - 1, NN = n * n, NP = (n - 1) * n * (n + 1) / 6;
-  constexpr int EPW = WaveMap<n>::EPW, SLOTS = 4 * EPW;
-  __shared__ T red[(SLOTS + 1) * NP * NN];
-  int slot, r;
-  bool lane_ok;
-  WaveMap<n>::map(threadIdx.x, slot, r, lane_ok);
-  const int e = blockIdx.x * SLOTS + slot;
-  const bool valid = lane_ok && e < E;
-  const int ee = valid ? e : 0;
+  constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
+  __shared__ T red[NP * 64];
+  const int lane = threadIdx.x & 63, l = threadIdx.x >> 6;
+  const int e = xcd_order(blockIdx.x, gridDim.x) * 64 + lane;
+  const bool valid = e < E;
+  const int ee = valid ? e : E - 1;   // idle lanes load in bounds and are masked
   const int ex = ee % N, ey = (ee / N) % N, ez = ee / (N * N);
-  const int j = r % n, l = r / n;
-  const int gy = ey * k + j, gz = ez * k + l;
-  T part[NP];
+  const int gz = ez * k + l;
+  const bool zin = valid && gz > 0 && gz < M - 1;
+  T gml[k], gxl[k];
+  local_weights<n, T>(l, gml, gxl);
+  T acc[NP];
 #pragma unroll
-  for (int m = 0; m < NP; ++m) part[m] = T(0);
-  if (valid && gy > 0 && gy < M - 1 && gz > 0 && gz < M - 1) {
+  for (int m = 0; m < NP; ++m) acc[m] = T(0);
+  // all lines' loads in flight at once up to order 3; one line at a time above (registers)
+#pragma unroll(n <= 4 ? n : 1)
+  for (int j = 0; j < n; ++j) {
+    const int gy = ey * k + j;
+    const bool row = zin && gy > 0 && gy < M - 1;
     const size_t gyz = (size_t)M * (gy + (size_t)M * gz);
     T uv[n][3], sv[n];
 #pragma unroll
@@ -1648,34 +1661,33 @@ k_div_line(const int N, const int M, const int E, const int nn, const T hh,
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       const int gx = ex * k + i;
-      const T s = (gx > 0 && gx < M - 1) ? sv[i] : T(0);
+      const T sc = (row && gx > 0 && gx < M - 1) ? sv[i] : T(0);
 #pragma unroll
       for (int a = 0; a < k; ++a) {
         const T mi = (T)CG<n>::t.GM[a * n + i], di = (T)CG<n>::t.GX[a * n + i];
-        R[0][a] += di * (s * uv[i][0]);
-        R[1][a] += mi * (s * uv[i][1]);
-        R[2][a] += mi * (s * uv[i][2]);
+        R[0][a] += di * (sc * uv[i][0]);
+        R[1][a] += mi * (sc * uv[i][1]);
+        R[2][a] += mi * (sc * uv[i][2]);
       }
     }
-    T gmj[k], gxj[k], gml[k], gxl[k];
+    T gmj[k], gxj[k];
     local_weights<n, T>(j, gmj, gxj);
-    local_weights<n, T>(l, gml, gxl);
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
       const int a = CT<n>::t.ma[m], b = CT<n>::t.mb[m], c = CT<n>::t.mc[m];
-      part[m] = R[0][a] * (gmj[b] * gml[c]) + R[1][a] * (gxj[b] * gml[c]) + R[2][a] * (gmj[b] * gxl[c]);
+      acc[m] += R[0][a] * (gmj[b] * gml[c]) + R[1][a] * (gxj[b] * gml[c]) +
+                R[2][a] * (gmj[b] * gxl[c]);
     }
   }
-  T* rs = red + (lane_ok ? slot : SLOTS) * NP * NN;
+  for (int w = 0; w < n; ++w) {
+    if (l == w) {
 #pragma unroll
-  for (int m = 0; m < NP; ++m) rs[m * NN + r] = part[m];
-  wave_sync();
-  if (valid && r < NP) {
-    T acc = T(0);
-#pragma unroll
-    for (int q = 0; q < NN; ++q) acc += rs[r * NN + q];
-    emit<EP>(ep, (size_t)e * NP + r, -hh * hh * acc, pout, add);
+      for (int m = 0; m < NP; ++m) red[m * 64 + lane] = (w == 0 ? T(0) : red[m * 64 + lane]) + acc[m];
+    }
+    __syncthreads();
   }
+  if (valid)
+    for (int m = l; m < NP; m += n) emit<EP>(ep, (size_t)e * NP + m, -hh * hh * red[m * 64 + lane], pout, add);
 }
 
 // Sum the partial values on internal brick planes into y (x planes, then y planes not on an
@@ -1797,7 +1809,7 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
     constexpr int SLOTS = 4 * WaveMap<n>::EPW;
     ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
     if constexpr (MF == 0 && (F & F_DIR) != 0)
-      hipLaunchKernelGGL((k_div_line<n, T, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st, N, M, E,
+      hipLaunchKernelGGL((k_div_elem<n, T, EP>), dim3(grid_for(E, 64)), dim3(64 * n), 0, st, N, M, E,
                          nn, hh, u, sin, pout, (int)add, ep);
     else
       hipLaunchKernelGGL((k_op_gather<n, T, F, MF, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st,
@@ -2556,6 +2568,55 @@ __global__ void k_kron(int Mo, int Mi, int NC, int W, const int* __restrict__ cn
   out[idx] = add ? out[idx] + (T)s : (T)s;
 }
 
+// The same transfer with at most WM entries per 1D row (the same 1D rows serve the three
+// directions).  The block first copies the rows into LDS (padded entries repeat a valid column
+// with weight 0), so that the per-output row lookups cost no memory instructions; every input
+// load is unconditional, and each output sums x first, then weights by its y and z entries.
+// Grid: (plane of Mo^2 outputs, groups of zb of the Mo NC z-planes); 32-bit index arithmetic;
+// dynamic LDS of Mo WM (int + double).
+template <typename T, int WM>
+__global__ void __launch_bounds__(256)
+k_kron_fixed(int Mo, int Mi, int NC, int W, const int* __restrict__ cnt, const int* __restrict__ col,
+             const double* __restrict__ val, int dir, int add, int zb, const T* __restrict__ in,
+             T* __restrict__ out) {
+  extern __shared__ double kron_lds[];
+  double* lv = kron_lds;                                // [Mo][WM] weights
+  int* lc = reinterpret_cast<int*>(lv + Mo * WM);       // [Mo][WM] columns
+  for (int q = threadIdx.x; q < Mo * WM; q += blockDim.x) {
+    const int r = q / WM, t = q % WM, nr = cnt[r];
+    const int tt = min(t, max(nr - 1, 0));
+    lc[q] = col[r * W + tt];
+    lv[q] = t < nr ? val[r * W + tt] : 0.0;
+  }
+  __syncthreads();
+  const int pl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pl >= Mo * Mo) return;
+  const int oi = pl % Mo, oj = pl / Mo;
+  const size_t ni = (size_t)Mi * Mi * Mi;
+  const int z1 = min((int)(blockIdx.y + 1) * zb, Mo * NC);
+  for (int zc = blockIdx.y * zb; zc < z1; ++zc) {
+    const int c = zc / Mo, ol = zc % Mo;
+    const size_t idx = ((size_t)zc * Mo) * Mo + pl;
+    if (dir && (oi == 0 || oi == Mo - 1 || oj == 0 || oj == Mo - 1 || ol == 0 || ol == Mo - 1)) {
+      if (!add) out[idx] = T(0);
+      continue;
+    }
+    const T* inc = in + (size_t)c * ni;
+    double s = 0.0;
+#pragma unroll
+    for (int tc = 0; tc < WM; ++tc)
+#pragma unroll
+      for (int tb = 0; tb < WM; ++tb) {
+        const T* line = inc + ((size_t)lc[ol * WM + tc] * Mi + lc[oj * WM + tb]) * Mi;
+        double sx = 0.0;
+#pragma unroll
+        for (int ta = 0; ta < WM; ++ta) sx += lv[oi * WM + ta] * (double)line[lc[oi * WM + ta]];
+        s += (lv[ol * WM + tc] * lv[oj * WM + tb]) * sx;
+      }
+    out[idx] = add ? out[idx] + (T)s : (T)s;
+  }
+}
+
 // Linear interpolation between nested node grids, M_fine = 2 M_coarse - 1, and its transpose.
 // Prolongation: the fine node value is the mean of the coarse values at the 8 corners
 // (x0|x1) x (y0|y1) x (z0|z1), x0 = fx / 2, x1 = x0 + (fx odd): 1 at shared nodes, 1/2 along a
@@ -2644,7 +2705,7 @@ template <int n, typename T>
 __global__ void __launch_bounds__(256)
 k_modal_IT(const int N, const int M, const T* __restrict__ p, T* __restrict__ u) {
   constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= N * M * M) return;
   const int ex = t % N, gy = (t / N) % M, gz = t / (N * M);
   int yc[2], zc[2];
@@ -2951,6 +3012,77 @@ __global__ void __launch_bounds__(256) k_rows_sum(int nb, const double* __restri
   for (int i = threadIdx.x; i < nb; i += blockDim.x) s += p[i];
   s = block_sum(s);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// The update of the first classical Gram-Schmidt sweep fused with the projections of the
+// second: w -= V h, then partials of V[v] . w for the updated w, from one read of V.  Rows go in
+// chunks of GS_ROWS staged in LDS ([nv][GS_ROWS + 1], padded against bank conflicts), the loads
+// of the next chunk in registers while the current one is worked on: each row is summed over
+// the vectors in four interleaved partial sums (wave q takes v = q mod 4), added in a fixed
+// order; then threads 2v and 2v + 1 accumulate V[v] . w over the even and the odd rows.
+// partial[v * gridDim.x + block], as k_mdot_partial.
+// PER: the vectors per wave the kernel is built for (nv <= 4 PER); loads are unconditional, with
+// clamped indices, so that none waits behind a branch.
+constexpr int GS_ROWS = 64, GS_MAX_NV = 120;
+template <int PER>
+__global__ void __launch_bounds__(256) k_gs_sub_dot(size_t n, int nv, const double* __restrict__ V,
+                                                    size_t ld, const double* __restrict__ h,
+                                                    double* __restrict__ w,
+                                                    double* __restrict__ partial) {
+  extern __shared__ double sh[];
+  constexpr int LS = GS_ROWS + 1;
+  double* vs = sh;                                  // [nv][LS]
+  double* ws = vs + (size_t)nv * LS;                // [GS_ROWS] updated w of the chunk
+  double* ps = ws + GS_ROWS;                        // [4][GS_ROWS] row partial sums
+  double* hs = ps + 4 * GS_ROWS;                    // [nv]
+  const int t = threadIdx.x, r = t % GS_ROWS, q = t / GS_ROWS;
+  for (int v = t; v < nv; v += blockDim.x) hs[v] = h[v];
+  const int dv = t >> 1, dp = t & 1;                // dot: vector dv, rows of parity dp
+  const bool dact = dv < nv;
+  double acc = 0.0;
+  double pre[PER];
+  double wpre = 0.0;
+  auto load = [&](size_t c0) {
+    const size_t i = min(c0 + r, n - 1);
+#pragma unroll
+    for (int s = 0; s < PER; ++s) pre[s] = V[(size_t)min(q + 4 * s, nv - 1) * ld + i];
+    wpre = w[i];
+  };
+  const size_t step = (size_t)gridDim.x * GS_ROWS;
+  size_t c0 = (size_t)blockIdx.x * GS_ROWS;
+  if (c0 < n) load(c0);
+  for (; c0 < n; c0 += step) {
+    __syncthreads();  // the previous chunk's LDS reads are done (and hs is written)
+    const size_t i = c0 + r;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int v = q + 4 * s;
+      if (v < nv) vs[v * LS + r] = i < n ? pre[s] : 0.0;
+    }
+    const double wcur = wpre;
+    __syncthreads();
+    if (c0 + step < n) load(c0 + step);
+    double sum = 0.0;
+    for (int v = q; v < nv; v += 4) sum += vs[v * LS + r] * hs[v];
+    ps[q * GS_ROWS + r] = sum;
+    __syncthreads();
+    if (q == 0) {
+      const double wn =
+          wcur - (((ps[r] + ps[GS_ROWS + r]) + ps[2 * GS_ROWS + r]) + ps[3 * GS_ROWS + r]);
+      if (i < n) w[i] = wn;
+      ws[r] = i < n ? wn : 0.0;
+    }
+    __syncthreads();
+    if (dact) {
+      const double* row = vs + dv * LS + dp;
+#pragma unroll 8
+      for (int rr = 0; rr < GS_ROWS / 2; ++rr) acc += row[2 * rr] * ws[2 * rr + dp];
+    }
+  }
+  __syncthreads();
+  if (dact) ps[t] = acc;
+  __syncthreads();
+  if (t < nv) partial[(size_t)t * gridDim.x + blockIdx.x] = ps[2 * t] + ps[2 * t + 1];
 }
 
 __global__ void k_gemv(size_t n, int nv, const double* __restrict__ V, size_t ld,
@@ -3318,8 +3450,25 @@ void launch_kron(hipStream_t st, const Rows1D& R, int NC, bool dir, bool add, co
                          R.cols, NC, (int)dir, (int)add, in, out);
     return;
   }
-  hipLaunchKernelGGL((k_kron<T>), dim3(grid_for(tot, 256)), dim3(256), 0, st, R.rows, R.cols, NC,
-                     R.W, R.cnt, R.col, R.val, (int)dir, (int)add, in, out);
+  // z-planes per block: up to 8 (fewer table copies), while the grid keeps >= 4096 blocks
+  const size_t pb = grid_for((size_t)R.rows * R.rows, 256), planes = (size_t)R.rows * NC;
+  const int zb = (int)std::max<size_t>(1, std::min<size_t>(8, pb * planes / 4096));
+  const dim3 g(pb, grid_for(planes, zb)), b(256);
+  const int wm = R.W <= 2 ? 2 : R.W <= 3 ? 3 : R.W <= 4 ? 4 : R.W <= 7 ? 7 : 0;
+  const size_t lds = (size_t)R.rows * wm * (sizeof(double) + sizeof(int));
+  if (wm == 0 || lds > 48u * 1024u) {
+    hipLaunchKernelGGL((k_kron<T>), dim3(grid_for(tot, 256)), b, 0, st, R.rows, R.cols, NC, R.W,
+                       R.cnt, R.col, R.val, (int)dir, (int)add, in, out);
+    return;
+  }
+#define WB_KRON(WMV)                                                                               \
+  hipLaunchKernelGGL((k_kron_fixed<T, WMV>), g, b, lds, st, R.rows, R.cols, NC, R.W, R.cnt, R.col, \
+                     R.val, (int)dir, (int)add, zb, in, out)
+  if (wm == 2) WB_KRON(2);
+  else if (wm == 3) WB_KRON(3);
+  else if (wm == 4) WB_KRON(4);
+  else WB_KRON(7);
+#undef WB_KRON
 }
 template void launch_kron<double>(hipStream_t, const Rows1D&, int, bool, bool, const double*, double*);
 template void launch_kron<float>(hipStream_t, const Rows1D&, int, bool, bool, const float*, float*);
@@ -3452,6 +3601,33 @@ void launch_mdot(hipStream_t st, size_t n, int nv, const double* V, size_t ld, c
   const int ng = (nv + MDOT_VG - 1) / MDOT_VG;
   hipLaunchKernelGGL(k_mdot_partial, dim3(nb, ng), dim3(256), 0, st, n, nv, V, ld, w, partial);
   hipLaunchKernelGGL(k_rows_sum, dim3(nv), dim3(256), 0, st, nb, partial, h);
+}
+bool launch_gs_sub_dot(hipStream_t st, size_t n, int nv, const double* V, size_t ld,
+                       const double* h, double* w, double* partial, double* h2) {
+  if (nv > GS_MAX_NV || nv < 1 || n < 1) return false;
+  const size_t lds = sizeof(double) * ((size_t)nv * (GS_ROWS + 1) + 5 * GS_ROWS + nv);
+  // as many blocks as are resident at once (the LDS bounds them), at most MDOT_BLOCKS
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return false;
+  // the smallest build with 4 PER >= nv (padded loads repeat the last vector)
+  using K = void (*)(size_t, int, const double*, size_t, const double*, double*, double*);
+  static const K tiers[] = {k_gs_sub_dot<2>,  k_gs_sub_dot<4>,  k_gs_sub_dot<6>,  k_gs_sub_dot<8>,
+                            k_gs_sub_dot<10>, k_gs_sub_dot<12>, k_gs_sub_dot<14>, k_gs_sub_dot<16>,
+                            k_gs_sub_dot<20>, k_gs_sub_dot<24>, k_gs_sub_dot<30>};
+  static const int per[] = {2, 4, 6, 8, 10, 12, 14, 16, 20, 24, 30};
+  int ti = 0;
+  while (4 * per[ti] < nv) ++ti;
+  const K kern = tiers[ti];
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess ||
+      per_cu < 1)
+    return false;
+  const int nb = (int)std::min<size_t>({(size_t)MDOT_BLOCKS, (size_t)cus * per_cu,
+                                        std::max<size_t>(1, grid_for(n, GS_ROWS))});
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(256), lds, st, n, nv, V, ld, h, w, partial);
+  hipLaunchKernelGGL(k_rows_sum, dim3(nv), dim3(256), 0, st, nb, partial, h2);
+  return true;
 }
 void launch_gemv_sub(hipStream_t st, size_t n, int nv, const double* V, size_t ld, const double* h,
                      double* w) {

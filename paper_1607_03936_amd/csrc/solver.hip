@@ -1281,8 +1281,10 @@ wb_status fgmres_core(Solver& s, size_t n, const double* b, MatVec&& matvec, Pre
       precond(vj, zj);
       matvec(zj, s.w);
       launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, hb);
-      launch_gemv_sub(st, n, j + 1, s.V, n, hb, s.w);
-      launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, hb + (R + 2));
+      if (!launch_gs_sub_dot(st, n, j + 1, s.V, n, hb, s.w, s.mpartial, hb + (R + 2))) {
+        launch_gemv_sub(st, n, j + 1, s.V, n, hb, s.w);
+        launch_mdot(st, n, j + 1, s.V, n, s.w, s.mpartial, hb + (R + 2));
+      }
       launch_gemv_sub(st, n, j + 1, s.V, n, hb + (R + 2), s.w);
       launch_dot<double>(st, n, s.w, s.w, s.red_partial, hb + 2 * (R + 2));
       WB_HIP(hipMemcpyAsync(s.hpin + (size_t)(j & 1) * hs, hb, sizeof(double) * hs,
