@@ -6,10 +6,10 @@ python -m paper_1607_03936_amd.trafficsummary <out.json> <workload> <fetch.csv> 
 Each workload names the counter_collection.csv of its FETCH_SIZE run and of its WRITE_SIZE run
 (opbench.py <workload> <reps> copy).  The copy leg moves a known number of bytes (the velocity
 vector, read once and written once), so bytes / counter gives each counter's unit; the factors of
-all workloads are averaged.  An A apply is two kernels (the brick scatter and its face sums, or
-the element pass and its node sums); prints a text summary of both and writes the per-apply
-bytes of the pair to <out.json>, keyed like bench.py's kernel keys, with the source hash of the
-kernels the counters were taken on.
+all workloads are averaged.  An A apply is two kernels (the brick scatter, on the matrix cores or
+with LDS lines, and its face sums, or the element pass and its node sums); prints a text summary
+of both and writes the per-apply bytes of the pair to <out.json>, keyed like bench.py's kernel
+keys, with the source hash of the kernels the counters were taken on.
 """
 from __future__ import annotations
 
@@ -24,7 +24,7 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-A_KERNEL = re.compile(r"k_op_(brick|elem)<(\d), 3, double, 9, 0, 0>")
+A_KERNEL = re.compile(r"k_op_(brick|elem)<\d, 3, double, 9, 0, 0>|k_op_(mfma)<3, double, 9, 0>")
 FACE_KERNEL = re.compile(r"k_(face|node)_sum<(\d), 3, double, true, 0>")
 
 
@@ -48,7 +48,8 @@ def read(path):
                 copies.append((int(row["Grid_Size"]), val))
             elif A_KERNEL.search(name):
                 per["A"].append(val)
-                names["A"] = A_KERNEL.search(name).group(1)
+                mt = A_KERNEL.search(name)
+                names["A"] = mt.group(1) or mt.group(2)
             elif FACE_KERNEL.search(name):
                 per["face"].append(val)
                 names["face"] = FACE_KERNEL.search(name).group(1)
@@ -102,7 +103,8 @@ def main(argv):
             tot["write_kib"] += wk
             tot["bytes"] += rd + wr
             if cls == "A":
-                label = f"k_op_{form}<{w.k + 1},3,double,9,0,0>"
+                label = (f"k_op_mfma<3,double,9,0>" if form == "mfma"
+                         else f"k_op_{form}<{w.k + 1},3,double,9,0,0>")
             else:
                 label = f"k_{fper['names'].get('face', 'face')}_sum (same applies)"
             print(f"{name:<10} {label:<30} {len(fper[cls]):>5} {fk:>10.0f} {wk:>10.0f} {rd / 1e6:>9.2f} "
