@@ -17,6 +17,7 @@ import scipy.sparse.linalg as spla
 import sympy as sy
 
 from oracle import fem
+from synthetic import random_vector
 
 X, Y, Z = sy.symbols("x y z")
 
@@ -195,3 +196,56 @@ def test_apply_A_rows_equal_assembled_rows(k):
     got = fem.apply_A_rows(m, lambda els: mu[els], u, dofs)
     want = A[dofs] @ u
     assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("N,k", [(2, 2), (2, 3), (1, 4)])
+def test_modal_restriction_equals_lumped_mass_projection_of_residuals(N, k):
+    """The modal <-> nodal transfer of the K_w multigrid (Sec. 6) is an L2 projection with a
+    lumped nodal mass.  For a residual (a dual vector r over the pressure modes) the projection
+    onto the continuous nodal space and back to a dual vector is
+        M~_Q (M~_Q^-1 G^T M_psi^-1 r) = G^T M_psi^-1 r,
+    G[m, i] = int psi_m phi_i, M_psi = diag(int psi_m^2) (orthogonal modes): the lumping cancels
+    and the result is I^T r, I the element-wise L2 projection the oracle uses.  G, M_psi and the
+    lumped M~_Q are built here from a tensor Gauss rule of 2k+4 points, numpy's Legendre series
+    and the Lagrange product formula on GLL nodes found as roots of (1 - x^2) P_k'."""
+    from numpy.polynomial import legendre as L
+    m = fem.Mesh(N, k)
+    n, M, h = k + 1, m.M, 1.0 / N
+    dk = L.legder(np.eye(k + 1)[k])
+    gll = np.sort(np.concatenate([[-1.0, 1.0], L.legroots(dk)]))
+    xq, wq = L.leggauss(2 * k + 4)
+
+    def lag(i, x):
+        v = np.ones_like(x)
+        for j in range(n):
+            if j != i:
+                v = v * (x - gll[j]) / (gll[i] - gll[j])
+        return v
+
+    def leg(a, x):
+        return L.legval(x, np.eye(a + 1)[a])
+
+    B = np.array([lag(i, xq) for i in range(n)])            # [node, q]
+    P = np.array([leg(a, xq) for a in range(k)])            # [mode, q]
+    jac = (h / 2) ** 3
+    G1 = (B[None, :, :] * P[:, None, :] * wq).sum(-1)       # 1D int P_a l_i
+    Mp1 = (P * P * wq).sum(-1)                              # 1D int P_a^2
+    int1 = (B * wq).sum(-1)                                 # 1D int l_i
+    r = random_vector(77, m.p_dof)
+    lumped = np.zeros(m.n_nodes)
+    Gt_r = np.zeros(m.n_nodes)
+    for e in range(m.E):
+        ex, ey, ez = e % N, (e // N) % N, e // (N * N)
+        for c in range(n):
+            for b in range(n):
+                for a in range(n):
+                    g = (ex * k + a) + M * ((ey * k + b) + M * (ez * k + c))
+                    lumped[g] += jac * int1[a] * int1[b] * int1[c]
+                    for mi, (pa, pb, pc) in enumerate(m.modes):
+                        Gmi = jac * G1[pa, a] * G1[pb, b] * G1[pc, c]
+                        Mpsi = jac * Mp1[pa] * Mp1[pb] * Mp1[pc]
+                        Gt_r[g] += Gmi * r[e * m.n_p + mi] / Mpsi
+    projected = Gt_r / lumped                               # nodal function, lumped projection
+    dual = lumped * projected
+    want = fem.modal_projection(m).T @ r
+    assert np.allclose(dual, want, rtol=0, atol=1e-13 * np.abs(want).max())
