@@ -3019,7 +3019,7 @@ __global__ void __launch_bounds__(256) k_rows_sum(int nb, const double* __restri
 // chunks of GS_ROWS staged in LDS ([nv][GS_ROWS + 1], padded against bank conflicts), the loads
 // of the next chunk in registers while the current one is worked on: each row is summed over
 // the vectors in four interleaved partial sums (wave q takes v = q mod 4), added in a fixed
-// order; then threads 2v and 2v + 1 accumulate V[v] . w over the even and the odd rows.
+// order; then TPV threads per vector accumulate V[v] . w over interleaved rows.
 // partial[v * gridDim.x + block], as k_mdot_partial.
 // PER: the vectors per wave the kernel is built for (nv <= 4 PER); loads are unconditional, with
 // clamped indices, so that none waits behind a branch.
@@ -3037,7 +3037,11 @@ __global__ void __launch_bounds__(256) k_gs_sub_dot(size_t n, int nv, const doub
   double* hs = ps + 4 * GS_ROWS;                    // [nv]
   const int t = threadIdx.x, r = t % GS_ROWS, q = t / GS_ROWS;
   for (int v = t; v < nv; v += blockDim.x) hs[v] = h[v];
-  const int dv = t >> 1, dp = t & 1;                // dot: vector dv, rows of parity dp
+  // dot: TPV threads per vector (all 256 threads busy up to nv = 256 / TPV), thread dq of vector
+  // dv taking the rows dq, dq + TPV, ...
+  constexpr int TPV = PER <= 2 ? 32 : PER <= 4 ? 16 : PER <= 8 ? 8 : PER <= 16 ? 4 : 2;
+  static_assert(TPV * 4 * PER <= 256 && GS_ROWS % TPV == 0, "dot threads");
+  const int dv = t / TPV, dq = t % TPV;
   const bool dact = dv < nv;
   double acc = 0.0;
   double pre[PER];
@@ -3074,15 +3078,20 @@ __global__ void __launch_bounds__(256) k_gs_sub_dot(size_t n, int nv, const doub
     }
     __syncthreads();
     if (dact) {
-      const double* row = vs + dv * LS + dp;
-#pragma unroll 8
-      for (int rr = 0; rr < GS_ROWS / 2; ++rr) acc += row[2 * rr] * ws[2 * rr + dp];
+      const double* row = vs + dv * LS + dq;
+#pragma unroll
+      for (int rr = 0; rr < GS_ROWS / TPV; ++rr) acc += row[rr * TPV] * ws[rr * TPV + dq];
     }
   }
   __syncthreads();
   if (dact) ps[t] = acc;
   __syncthreads();
-  if (t < nv) partial[(size_t)t * gridDim.x + blockIdx.x] = ps[2 * t] + ps[2 * t + 1];
+  if (t < nv) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < TPV; ++q) sum += ps[t * TPV + q];
+    partial[(size_t)t * gridDim.x + blockIdx.x] = sum;
+  }
 }
 
 __global__ void k_gemv(size_t n, int nv, const double* __restrict__ V, size_t ld,
