@@ -695,33 +695,61 @@ __device__ inline void element_op(const bool valid, const int e, const int k, co
 }
 
 // What happens to a finished output value v of index j (see Epi in kernels.h); the mode is
-// a template constant, so a plain store carries none of the epilogue's arguments.
+// a template constant, so a plain store carries none of the epilogue's arguments.  The loads the
+// epilogue needs (epi_load) and the update itself (epi_store) are separate steps, so that a
+// kernel can issue the loads early; emit does both at once.
+template <typename T>
+struct EpiIn {
+  T b = T(0), r = T(0), dold = T(0), dinv = T(0), x = T(0);
+};
 template <int EP, typename T>
-__device__ __forceinline__ void emit(const Epi<T>& e, const size_t j, const T v, T* __restrict__ y,
-                                     const int add) {
+__device__ __forceinline__ EpiIn<T> epi_load(const Epi<T>& e, const size_t j,
+                                             const T* __restrict__ y, const int add) {
+  EpiIn<T> q;
   if constexpr (EP == EPI_RESID) {
-    e.r[j] = e.b[j] - v;
+    q.b = e.b[j];
+  } else if constexpr (EP == EPI_CHEB_FIRST || EP == EPI_CHEB_ZERO) {
+    q.b = e.b[j];
+    q.dinv = e.dinv[j];
+  } else if constexpr (EP == EPI_CHEB_STEP) {
+    q.r = e.r[j];
+    q.dold = e.dold[j];
+    q.dinv = e.dinv[j];
+    q.x = e.x[j];
+  }
+  return q;   // the plain store reads y (when it adds) in epi_store
+}
+template <int EP, typename T>
+__device__ __forceinline__ void epi_store(const Epi<T>& e, const size_t j, const T v,
+                                          const EpiIn<T>& q, T* __restrict__ y, const int add) {
+  if constexpr (EP == EPI_RESID) {
+    e.r[j] = q.b - v;
   } else if constexpr (EP == EPI_CHEB_FIRST) {
-    const T ri = e.b[j] - v;
+    const T ri = q.b - v;
     e.r[j] = ri;
-    e.dnew[j] = e.alpha * e.dinv[j] * ri;
+    e.dnew[j] = e.alpha * q.dinv * ri;
   } else if constexpr (EP == EPI_CHEB_ZERO) {
-    const T d0 = e.gamma * e.dinv[j] * e.b[j];
-    const T ri = e.b[j] - v;
+    const T d0 = e.gamma * q.dinv * q.b;
+    const T ri = q.b - v;
     e.r[j] = ri;
-    const T dn = e.alpha * d0 + e.beta * e.dinv[j] * ri;
+    const T dn = e.alpha * d0 + e.beta * q.dinv * ri;
     e.dnew[j] = dn;
     e.x[j] = d0 + dn;
   } else if constexpr (EP == EPI_CHEB_STEP) {
-    const T ri = e.r[j] - v;
+    const T ri = q.r - v;
     e.r[j] = ri;
-    const T d0 = e.dold[j];
-    const T dn = e.alpha * d0 + e.beta * e.dinv[j] * ri;
+    const T d0 = q.dold;
+    const T dn = e.alpha * d0 + e.beta * q.dinv * ri;
     e.dnew[j] = dn;
-    e.x[j] += e.add_old ? d0 + dn : dn;
+    e.x[j] = q.x + (e.add_old ? d0 + dn : dn);
   } else {
     y[j] = add ? y[j] + v : v;
   }
+}
+template <int EP, typename T>
+__device__ __forceinline__ void emit(const Epi<T>& e, const size_t j, const T v, T* __restrict__ y,
+                                     const int add) {
+  epi_store<EP>(e, j, v, epi_load<EP>(e, j, y, add), y, add);
 }
 
 // Brick geometry of the scatter kernel: a block owns a BX x BY tile of elements and marches
@@ -1679,6 +1707,15 @@ k_div_elem(const int N, const int M, const int E, const int nn, const T hh,
                 R[2][a] * (gmj[b] * gxl[c]);
     }
   }
+  // the epilogue's loads of this thread's outputs (modes l, l + n, ...) go out before the sums,
+  // so that their latency overlaps the reduction instead of following it
+  constexpr int MO = (NP + n - 1) / n;
+  EpiIn<T> pre[MO];
+#pragma unroll
+  for (int i = 0; i < MO; ++i) {
+    const int m = l + n * i;
+    if (valid && m < NP) pre[i] = epi_load<EP>(ep, (size_t)e * NP + m, pout, add);
+  }
   for (int w = 0; w < n; ++w) {
     if (l == w) {
 #pragma unroll
@@ -1686,8 +1723,12 @@ k_div_elem(const int N, const int M, const int E, const int nn, const T hh,
     }
     __syncthreads();
   }
-  if (valid)
-    for (int m = l; m < NP; m += n) emit<EP>(ep, (size_t)e * NP + m, -hh * hh * red[m * 64 + lane], pout, add);
+#pragma unroll
+  for (int i = 0; i < MO; ++i) {
+    const int m = l + n * i;
+    if (valid && m < NP)
+      epi_store<EP>(ep, (size_t)e * NP + m, -hh * hh * red[m * 64 + lane], pre[i], pout, add);
+  }
 }
 
 // Sum the partial values on internal brick planes into y (x planes, then y planes not on an
