@@ -1247,6 +1247,11 @@ k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
     }
   }
   const int colg = gi + M * gj;
+  // plain stores (no add): node, face slot and Dirichlet zero are one store sequence per lane,
+  // with a per-lane destination, component stride and plane stride (no divergent branches)
+  T* const dptr = kind == K_FACE ? face + base : y + colg;
+  const size_t cstr = kind == K_FACE ? G.per_comp : (size_t)nn;
+  const size_t zstr = kind == K_FACE ? (size_t)M : (size_t)M * M;
   auto store = [&](const double (&vd)[NC], int gz, bool general) {
     T val[NC];
 #pragma unroll
@@ -1254,6 +1259,12 @@ k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
     if (general) {
       if (owner)
         store_node<4, NC, T, DIR, EO>(G, gi, gj, gz, X0, Y0, Z0, X1, Y1, Z1, val, y, face, add, ep);
+    } else if (EO == EPI_STORE && !add) {
+      if (kind != K_SKIP) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          dptr[(size_t)c * cstr + zstr * gz] = kind == K_ZERO ? T(0) : val[c];
+      }
     } else if (kind == K_NODE) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
