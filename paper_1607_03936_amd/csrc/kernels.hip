@@ -1174,7 +1174,7 @@ __device__ __forceinline__ double from_left(double v) {
 // formed as it is read (the operator half of EPI_CHEB_ZERO, whose epilogue then runs apart).
 constexpr int EPI_ZERO_IN = 5;
 template <int NC, typename T, int F, int EP>
-__global__ void __launch_bounds__(MF_NT, 2)
+__global__ void __launch_bounds__(MF_NT, NC == 1 ? 4 : 2)
 k_op_mfma(const BrickDev G, const double hh, const T* __restrict__ u,
           T* __restrict__ y, const T* __restrict__ coef,
           const T* __restrict__ sin_, T* __restrict__ face, const int add,
