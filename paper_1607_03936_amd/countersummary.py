@@ -8,6 +8,7 @@ each counter per dispatch over all given runs, then
   MFMA busy %     100 SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x 256 CUs x 4 SIMDs)
                   (GRBM_GUI_ACTIVE is reported summed over the eight XCDs)
   FP64 MFMA rate  512 SQ_INSTS_VALU_MFMA_MOPS_F64 flops / duration, against 78.6 TFLOP/s
+  BF16 MFMA rate  512 SQ_INSTS_VALU_MFMA_MOPS_BF16 flops / duration, against 2500 TFLOP/s (dense)
   LDS conflict %  100 SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE
   L2 hit %        100 TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)
 """
@@ -20,6 +21,7 @@ from collections import defaultdict
 
 XCDS, CUS, SIMDS = 8, 256, 4
 F64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def short(name: str) -> str:
@@ -57,13 +59,17 @@ def summarize(pattern: str, paths) -> str:
         out.append(f"{k}: {len(durs[k])} dispatches over the runs, mean duration {dur_ns / 1e3:.1f} us")
         for n in sorted(c):
             out.append(f"  {n:<32} {c[n]:>16.1f}  per dispatch")
-        if "SQ_VALU_MFMA_BUSY_CYCLES" in c and "GRBM_GUI_ACTIVE" in c:
+        if c.get("SQ_VALU_MFMA_BUSY_CYCLES") and "GRBM_GUI_ACTIVE" in c:
             cyc = c["GRBM_GUI_ACTIVE"] / XCDS
             out.append(f"  MFMA busy                        {100 * c['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * CUS * SIMDS):>15.1f} %")
-        if "SQ_INSTS_VALU_MFMA_MOPS_F64" in c:
+        if c.get("SQ_INSTS_VALU_MFMA_MOPS_F64"):
             tf = 512 * c["SQ_INSTS_VALU_MFMA_MOPS_F64"] / dur_ns / 1e3
             out.append(f"  FP64 MFMA rate                   {tf:>15.2f} TFLOP/s "
                        f"({100 * tf / F64_PEAK_TFLOPS:.1f} % of {F64_PEAK_TFLOPS})")
+        if c.get("SQ_INSTS_VALU_MFMA_MOPS_BF16"):
+            tb = 512 * c["SQ_INSTS_VALU_MFMA_MOPS_BF16"] / dur_ns / 1e3
+            out.append(f"  BF16 MFMA rate                   {tb:>15.2f} TFLOP/s "
+                       f"({100 * tb / BF16_PEAK_TFLOPS:.2f} % of {BF16_PEAK_TFLOPS:g})")
         if "SQ_LDS_BANK_CONFLICT" in c and c.get("SQ_LDS_IDX_ACTIVE"):
             out.append(f"  LDS bank conflict                {100 * c['SQ_LDS_BANK_CONFLICT'] / c['SQ_LDS_IDX_ACTIVE']:>15.1f} % of LDS cycles")
         if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
