@@ -1747,36 +1747,36 @@ k_div_elem(const int N, const int M, const int E, const int nn, const T hh,
 template <int n, int NC, typename T, bool DIR, int EP>
 __global__ void k_face_sum(const BrickDev G, const T* __restrict__ face, T* __restrict__ y,
                            const int add, const Epi<T> ep) {
-  const int M = G.M;
-  const long long nx = (long long)(G.nbx - 1) * M * M, ny = (long long)(G.nby - 1) * M * M;
-  const long long nz = (long long)(G.nbz - 1) * M * M;
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // 32-bit index arithmetic: the face nodes number (nbx + nby + nbz - 3) M^2 < 2^31
+  const int M = G.M, MM = M * M;
+  const int nx = (G.nbx - 1) * MM, ny = (G.nby - 1) * MM, nz = (G.nbz - 1) * MM;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nx + ny + nz) return;
   constexpr int k = n - 1, KX = k * Tile<n>::BX, KY = k * Tile<n>::BY;
   const int KZ = k * G.Bz;
   int gx, gy, gz, cat, b;
   if (idx < nx) {
     cat = 0;
-    b = (int)(idx / ((long long)M * M));
-    const long long rem = idx % ((long long)M * M);
-    gz = (int)(rem / M);
-    gy = (int)(rem % M);
+    b = idx / MM;
+    const int rem = idx - b * MM;
+    gz = rem / M;
+    gy = rem - gz * M;
     gx = (b + 1) * KX;
   } else if (idx < nx + ny) {
     idx -= nx;
     cat = 1;
-    b = (int)(idx / ((long long)M * M));
-    const long long rem = idx % ((long long)M * M);
-    gz = (int)(rem / M);
-    gx = (int)(rem % M);
+    b = idx / MM;
+    const int rem = idx - b * MM;
+    gz = rem / M;
+    gx = rem - gz * M;
     gy = (b + 1) * KY;
   } else {
     idx -= nx + ny;
     cat = 2;
-    b = (int)(idx / ((long long)M * M));
-    const long long rem = idx % ((long long)M * M);
-    gy = (int)(rem / M);
-    gx = (int)(rem % M);
+    b = idx / MM;
+    const int rem = idx - b * MM;
+    gy = rem / M;
+    gx = rem - gy * M;
     gz = (b + 1) * KZ;
   }
   const bool on_x = gx % KX == 0 && gx > 0 && gx < M - 1;
@@ -2731,21 +2731,45 @@ k_lin21(const int Mo, const int Mi, const int NC, const int dir, const int add,
 }
 
 template <int n, typename T>
-__global__ void k_modal_I(const KT<n, T> tb, int N, int k, int M, int E, const T* __restrict__ u,
-                          T* __restrict__ p, int add) {
-  constexpr int NN = n * n, N3 = NN * n, NP = (n - 1) * n * (n + 1) / 6;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)E * NP) return;
-  const int e = (int)(idx / NP), m = (int)(idx % NP);
+__global__ void __launch_bounds__(256)
+k_modal_I(const int N, const int M, const int E, const T* __restrict__ u, T* __restrict__ p,
+          const int add) {
+  // one thread per element, consecutive threads on consecutive elements in x (each load
+  // instruction covers a contiguous run of nodes); per node line (b, c) the x contraction
+  // R[a'] = sum_a J[a'][a] u[a, b, c] first, then each mode takes J[mb][b] J[mc][c] R[ma]
+  constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
   const int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
-  const int ma = tb.ma[m], mb = tb.mb[m], mc = tb.mc[m];
-  T s = T(0);
-  for (int li = 0; li < N3; ++li) {
-    const int a = li % n, b = (li / n) % n, c = li / NN;
-    const int g = (ex * k + a) + M * ((ey * k + b) + M * (ez * k + c));
-    s += tb.J[ma * n + a] * tb.J[mb * n + b] * tb.J[mc * n + c] * u[g];
+  T acc[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) acc[m] = T(0);
+#pragma unroll
+  for (int c = 0; c < n; ++c)
+#pragma unroll
+    for (int b = 0; b < n; ++b) {
+      const T* row = u + (size_t)ex * k + (size_t)M * ((size_t)(ey * k + b) + (size_t)M * (ez * k + c));
+      T uv[n];
+#pragma unroll
+      for (int a = 0; a < n; ++a) uv[a] = row[a];
+      T R[k];
+#pragma unroll
+      for (int ma = 0; ma < k; ++ma) {
+        T r = T(0);
+#pragma unroll
+        for (int a = 0; a < n; ++a) r += (T)CT<n>::t.J[ma * n + a] * uv[a];
+        R[ma] = r;
+      }
+#pragma unroll
+      for (int m = 0; m < NP; ++m)
+        acc[m] += (T)CT<n>::t.J[CT<n>::t.mb[m] * n + b] * (T)CT<n>::t.J[CT<n>::t.mc[m] * n + c] *
+                  R[CT<n>::t.ma[m]];
+    }
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const size_t j = (size_t)e * NP + m;
+    p[j] = add ? p[j] + acc[m] : acc[m];
   }
-  p[idx] = add ? p[idx] + s : s;
 }
 
 // Transpose of the element-wise projection onto the Legendre modes, u = I^T p on the continuous
@@ -3536,11 +3560,10 @@ template void launch_kron<float>(hipStream_t, const Rows1D&, int, bool, bool, co
 
 template <typename T>
 void launch_modal_I(hipStream_t st, int N, int k, const T* u, T* p, bool add) {
-  const int M = k * N + 1, E = N * N * N, np = tables(k).np;
+  const int M = k * N + 1, E = N * N * N;
   WB_BY_ORDER(k, {
-    auto tb = make_kt<n, T>(k);
-    hipLaunchKernelGGL((k_modal_I<n, T>), dim3(grid_for((size_t)E * np, 256)), dim3(256), 0, st, tb,
-                       N, k, M, E, u, p, (int)add);
+    hipLaunchKernelGGL((k_modal_I<n, T>), dim3(grid_for((size_t)E, 256)), dim3(256), 0, st, N, M, E,
+                       u, p, (int)add);
   });
 }
 template <typename T>
