@@ -1584,59 +1584,72 @@ __global__ void __launch_bounds__(256)
 k_grad_line(const int N, const int M, const int nn, const T hh, const T* __restrict__ p,
             T* __restrict__ y, const int add) {
   constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
-  const int t = xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (t >= N * M * M) return;
-  const int ex = t % N, gy = (t / N) % M, gz = t / (N * M);
-  T v[k][3];
+  // each thread contracts the modes of its own x element (ex) over y and z; the element on its
+  // left (ex - 1) is its left neighbour thread's, read from LDS.  Blocks overlap by one: thread 0
+  // only contracts the element left of the block's first output, threads 1..255 write outputs.
+  __shared__ T qs[3 * k][256];
+  const int t = xcd_order(blockIdx.x, gridDim.x) * (blockDim.x - 1) + (int)threadIdx.x - 1;
+  const bool valid = t >= 0 && t < N * M * M;
+  const int tt = valid ? t : 0;
+  const int ex = tt % N, gy = (tt / N) % M, gz = tt / (N * M);
+  const bool inner = valid && gy > 0 && gy < M - 1 && gz > 0 && gz < M - 1;
+  int y0, y1, z0, z1;
+  T fmy[2][k], fdy[2][k], fmz[2][k], fdz[2][k];
+  node_cands<n, T>(gy, N, y0, y1, fmy, fdy);
+  node_cands<n, T>(gz, N, z0, z1, fmz, fdz);
+  auto contract = [&](const int X, T (&Q)[3][k]) {
 #pragma unroll
-  for (int i = 0; i < k; ++i)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[i][c] = T(0);
-  if (gy > 0 && gy < M - 1 && gz > 0 && gz < M - 1) {
-    int y0, y1, z0, z1;
-    T fmy[2][k], fdy[2][k], fmz[2][k], fdz[2][k];
-    node_cands<n, T>(gy, N, y0, y1, fmy, fdy);
-    node_cands<n, T>(gz, N, z0, z1, fmz, fdz);
-    T Q[2][3][k];
-#pragma unroll
-    for (int X = 0; X < 2; ++X)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int a = 0; a < k; ++a) Q[X][c][a] = T(0);
-    const int xl = ex > 0 ? ex - 1 : ex;
+      for (int a = 0; a < k; ++a) Q[c][a] = T(0);
 #pragma unroll
     for (int sz = 0; sz < 2; ++sz)
 #pragma unroll
       for (int sy = 0; sy < 2; ++sy) {
-        const size_t row = (size_t)N * ((sy ? y1 : y0) + (size_t)N * (sz ? z1 : z0));
+        const T* pe = p + ((size_t)N * ((sy ? y1 : y0) + (size_t)N * (sz ? z1 : z0)) + X) * NP;
 #pragma unroll
-        for (int X = 0; X < 2; ++X) {
-          const T* pe = p + (row + (X ? ex : xl)) * NP;
-#pragma unroll
-          for (int m = 0; m < NP; ++m) {
-            const int a = CT<n>::t.ma[m], b = CT<n>::t.mb[m], c = CT<n>::t.mc[m];
-            const T pm = pe[m];
-            Q[X][0][a] += pm * (fmy[sy][b] * fmz[sz][c]);
-            Q[X][1][a] += pm * (fdy[sy][b] * fmz[sz][c]);
-            Q[X][2][a] += pm * (fmy[sy][b] * fdz[sz][c]);
-          }
+        for (int m = 0; m < NP; ++m) {
+          const int a = CT<n>::t.ma[m], b = CT<n>::t.mb[m], c = CT<n>::t.mc[m];
+          const T pm = pe[m];
+          Q[0][a] += pm * (fmy[sy][b] * fmz[sz][c]);
+          Q[1][a] += pm * (fdy[sy][b] * fmz[sz][c]);
+          Q[2][a] += pm * (fmy[sy][b] * fdz[sz][c]);
         }
       }
-    const T h2 = -hh * hh;
+  };
+  T Q1[3][k], Q0[3][k];
+  if (inner) {
+    contract(ex, Q1);
+  } else {
 #pragma unroll
-    for (int i = 0; i < k; ++i)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T acc = T(0);
-#pragma unroll
-        for (int a = 0; a < k; ++a) {
-          acc += Q[1][c][a] * (T)(c == 0 ? CG<n>::t.GX[a * n + i] : CG<n>::t.GM[a * n + i]);
-          if (i == 0) acc += Q[0][c][a] * (T)(c == 0 ? CG<n>::t.GX[a * n + k] : CG<n>::t.GM[a * n + k]);
-        }
-        v[i][c] = (i == 0 && ex == 0) ? T(0) : acc * h2;
-      }
+      for (int a = 0; a < k; ++a) Q1[c][a] = T(0);
   }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < k; ++a) qs[c * k + a][threadIdx.x] = Q1[c][a];
+  __syncthreads();
+  if (!valid || threadIdx.x == 0) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < k; ++a) Q0[c][a] = (inner && ex > 0) ? qs[c * k + a][threadIdx.x - 1] : T(0);
+  T v[k][3];
+  const T h2 = -hh * hh;
+#pragma unroll
+  for (int i = 0; i < k; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < k; ++a) {
+        acc += Q1[c][a] * (T)(c == 0 ? CG<n>::t.GX[a * n + i] : CG<n>::t.GM[a * n + i]);
+        if (i == 0) acc += Q0[c][a] * (T)(c == 0 ? CG<n>::t.GX[a * n + k] : CG<n>::t.GM[a * n + k]);
+      }
+      v[i][c] = (!inner || (i == 0 && ex == 0)) ? T(0) : acc * h2;
+    }
   const size_t base = (size_t)ex * k + (size_t)M * (gy + (size_t)M * gz);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1869,7 +1882,7 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
   } else if constexpr ((F & (F_A | F_B)) == 0 && (F & F_DIR) != 0 && NC == 3 && MF == 0 &&
                        EP == EPI_STORE) {
     ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
-    hipLaunchKernelGGL((k_grad_line<n, T>), dim3(grid_for((size_t)N * M * M, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_grad_line<n, T>), dim3(grid_for((size_t)N * M * M, 255)), dim3(256), 0, st,
                        N, M, nn, hh, pin, y, (int)add);
   } else {
     if constexpr ((F & (F_BT | F_B)) == 0) {
@@ -2781,9 +2794,14 @@ template <int n, typename T>
 __global__ void __launch_bounds__(256)
 k_modal_IT(const int N, const int M, const T* __restrict__ p, T* __restrict__ u) {
   constexpr int k = n - 1, NP = (n - 1) * n * (n + 1) / 6;
-  const int t = xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (t >= N * M * M) return;
-  const int ex = t % N, gy = (t / N) % M, gz = t / (N * M);
+  // each thread contracts the modes of its own x element over y and z; the left element's
+  // contraction is the left neighbour thread's, read from LDS.  Blocks overlap by one: thread 0
+  // only contracts the element left of the block's first output, threads 1..255 write outputs.
+  __shared__ T qs[k][256];
+  const int t = xcd_order(blockIdx.x, gridDim.x) * (blockDim.x - 1) + (int)threadIdx.x - 1;
+  const bool valid = t >= 0 && t < N * M * M;
+  const int tt = valid ? t : 0;
+  const int ex = tt % N, gy = (tt / N) % M, gz = tt / (N * M);
   int yc[2], zc[2];
   T jy[2][k], jz[2][k];
   const int gc[2] = {gy, gz};
@@ -2805,41 +2823,47 @@ k_modal_IT(const int N, const int M, const T* __restrict__ p, T* __restrict__ u)
       (d ? jz : jy)[1][a] = v1 ? (T)CT<n>::t.J[a * n] : T(0);
     }
   }
-  T Q[2][k];
+  auto contract = [&](const int X, T (&Q)[k]) {
 #pragma unroll
-  for (int X = 0; X < 2; ++X)
+    for (int a = 0; a < k; ++a) Q[a] = T(0);
 #pragma unroll
-    for (int a = 0; a < k; ++a) Q[X][a] = T(0);
-  const int xl = ex > 0 ? ex - 1 : ex;
+    for (int sz = 0; sz < 2; ++sz)
 #pragma unroll
-  for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-    for (int sy = 0; sy < 2; ++sy) {
-      const size_t row = (size_t)N * (yc[sy] + (size_t)N * zc[sz]);
-#pragma unroll
-      for (int X = 0; X < 2; ++X) {
-        const T* pe = p + (row + (X ? ex : xl)) * NP;
+      for (int sy = 0; sy < 2; ++sy) {
+        const T* pe = p + ((size_t)N * (yc[sy] + (size_t)N * zc[sz]) + X) * NP;
 #pragma unroll
         for (int m = 0; m < NP; ++m)
-          Q[X][CT<n>::t.ma[m]] += pe[m] * (jy[sy][CT<n>::t.mb[m]] * jz[sz][CT<n>::t.mc[m]]);
+          Q[CT<n>::t.ma[m]] += pe[m] * (jy[sy][CT<n>::t.mb[m]] * jz[sz][CT<n>::t.mc[m]]);
       }
-    }
-  const T lo = ex > 0 ? T(1) : T(0);
+  };
+  T Q1[k], Q0[k];
+  if (valid) {
+    contract(ex, Q1);
+  } else {
+#pragma unroll
+    for (int a = 0; a < k; ++a) Q1[a] = T(0);
+  }
+#pragma unroll
+  for (int a = 0; a < k; ++a) qs[a][threadIdx.x] = Q1[a];
+  __syncthreads();
+  if (!valid || threadIdx.x == 0) return;
+#pragma unroll
+  for (int a = 0; a < k; ++a) Q0[a] = ex > 0 ? qs[a][threadIdx.x - 1] : T(0);
   const size_t base = (size_t)ex * k + (size_t)M * (gy + (size_t)M * gz);
 #pragma unroll
   for (int i = 0; i < k; ++i) {
     T acc = T(0);
 #pragma unroll
     for (int a = 0; a < k; ++a) {
-      acc += Q[1][a] * (T)CT<n>::t.J[a * n + i];
-      if (i == 0) acc += lo * Q[0][a] * (T)CT<n>::t.J[a * n + k];
+      acc += Q1[a] * (T)CT<n>::t.J[a * n + i];
+      if (i == 0) acc += Q0[a] * (T)CT<n>::t.J[a * n + k];
     }
     u[base + i] = acc;
   }
   if (ex == N - 1) {
     T acc = T(0);
 #pragma unroll
-    for (int a = 0; a < k; ++a) acc += Q[1][a] * (T)CT<n>::t.J[a * n + k];
+    for (int a = 0; a < k; ++a) acc += Q1[a] * (T)CT<n>::t.J[a * n + k];
     u[base + k] = acc;
   }
 }
@@ -3570,7 +3594,7 @@ template <typename T>
 void launch_modal_IT(hipStream_t st, int N, int k, const T* p, T* u) {
   const int M = k * N + 1;
   WB_BY_ORDER(k, {
-    hipLaunchKernelGGL((k_modal_IT<n, T>), dim3(grid_for((size_t)N * M * M, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_modal_IT<n, T>), dim3(grid_for((size_t)N * M * M, 255)), dim3(256), 0, st,
                        N, M, p, u);
   });
 }
