@@ -1672,7 +1672,7 @@ k_grad_line(const int N, const int M, const int nn, const T hh, const T* __restr
 // line's nodes in x into R_c[a] and adds the line's share of every mode.  The n partial sums of
 // an element are added in LDS in the order l = 0..k and go out through the epilogue (pressure
 // outputs e n_p + m).
-template <int n, typename T, int EP>
+template <int n, typename T, int EP, bool SCALE>
 __global__ void __launch_bounds__(64 * n)
 k_div_elem(const int N, const int M, const int E, const int nn, const T hh,
            const T* __restrict__ u, const T* __restrict__ sin_, T* __restrict__ pout,
@@ -1703,7 +1703,8 @@ k_div_elem(const int N, const int M, const int E, const int nn, const T hh,
       const size_t gn = (size_t)ex * k + i + gyz;
 #pragma unroll
       for (int c = 0; c < 3; ++c) uv[i][c] = u[(size_t)c * nn + gn];
-      sv[i] = sin_ != nullptr ? sin_[gn] : T(1);
+      if constexpr (SCALE) sv[i] = sin_[gn];   // a template flag: no branch between the loads
+      else sv[i] = T(1);
     }
     T R[3][k];
 #pragma unroll
@@ -1874,8 +1875,12 @@ void op_launch_ep(hipStream_t st, int N, int k, const T* u, T* y, const T* coef,
     constexpr int SLOTS = 4 * WaveMap<n>::EPW;
     ProfScope ps(st, op_key(NC, k, N, Fk, sin != nullptr, sizeof(T), ""));
     if constexpr (MF == 0 && (F & F_DIR) != 0)
-      hipLaunchKernelGGL((k_div_elem<n, T, EP>), dim3(grid_for(E, 64)), dim3(64 * n), 0, st, N, M, E,
-                         nn, hh, u, sin, pout, (int)add, ep);
+      if (sin != nullptr)
+        hipLaunchKernelGGL((k_div_elem<n, T, EP, true>), dim3(grid_for(E, 64)), dim3(64 * n), 0, st, N,
+                           M, E, nn, hh, u, sin, pout, (int)add, ep);
+      else
+        hipLaunchKernelGGL((k_div_elem<n, T, EP, false>), dim3(grid_for(E, 64)), dim3(64 * n), 0, st,
+                           N, M, E, nn, hh, u, sin, pout, (int)add, ep);
     else
       hipLaunchKernelGGL((k_op_gather<n, T, F, MF, EP>), dim3(grid_for(E, SLOTS)), dim3(256), 0, st,
                          N, k, M, E, nn, hh, u, pout, sin, (int)add, ep);
