@@ -1995,9 +1995,14 @@ void op_dispatch_mf(hipStream_t st, int flags, int NC, int N, int k, const T* u,
         return op_launch<n, 3, T, F_A | F_DIR, MF>(st, N, k, u, y, coef, pin, pout, sin, add, work, ep);
       case F_A | F_BT | F_B | F_DIR:
         if constexpr (MF == 0) {
-          if constexpr (n == 6) {
-            // at this order the fused kernel spills: A, then B^T added, then B (same results up
-            // to rounding order)
+          // at order 5 the fused kernel spills, and at order 3 above the two-pass size the
+          // matrix-core A with the line kernels of B^T and B is faster than the fused LDS-line
+          // kernel: A, then B^T added, then B (same results up to rounding order)
+          bool split = n == 6;
+          if constexpr (n == 4)
+            split = matrix_core_ops.load(std::memory_order_relaxed) && !two_pass(3, N, k) &&
+                    ep.mode == EPI_STORE && sin == nullptr;
+          if (split) {
             WB_REQUIRE(ep.mode == EPI_STORE && sin == nullptr, WB_EUNSUPPORTED,
                        "fused Stokes operator: plain store only");
             op_launch<n, 3, T, F_A | F_DIR, MF>(st, N, k, u, y, coef, nullptr, nullptr, nullptr, add,
@@ -2006,7 +2011,7 @@ void op_dispatch_mf(hipStream_t st, int flags, int NC, int N, int k, const T* u,
                                                  true, work, ep);
             return op_launch<n, 3, T, F_B | F_DIR, MF>(st, N, k, u, nullptr, nullptr, nullptr, pout,
                                                        nullptr, false, work, ep);
-          } else {
+          } else if constexpr (n != 6) {
             return op_launch<n, 3, T, F_A | F_BT | F_B | F_DIR, MF>(st, N, k, u, y, coef, pin, pout,
                                                                     sin, add, work, ep);
           }

@@ -304,6 +304,39 @@ def test_apply_A_q3_matrix_core_form_matches_assembled(N):
 
 
 @pytest.mark.parametrize("N", [4, 11])
+def test_stokes_operator_q3_brick_forms_match_assembled(N):
+    # order 3 above the two-pass size: with the matrix cores the Stokes operator runs as the
+    # matrix-core A, then B^T added, then B; without them as the fused LDS-line kernel
+    wb = _wb()
+    om = fem.Mesh(N, 3)
+    rng = np.random.default_rng(60 + N)
+    mu_q = 10.0 ** rng.uniform(-4, 4, (om.E, om.n ** 3))
+    m = wb.Mesh(N, 3)
+    v = wb.Viscosity.values(m, dev(mu_q.ravel()), dev(np.ones(om.n_nodes)))
+    u = random_vector(15, om.u_dof)
+    p = random_vector(16, om.p_dof)
+    ui = u.copy()
+    ui[om.vel_boundary] = 0.0
+    B = fem.assemble_B(om)
+    wu = fem.assemble_A(om, mu_q) @ ui + B.T @ p
+    wu[om.vel_boundary] = 0.0
+    wp = B @ ui
+    prev_limit = wb.wb_set_two_pass_limit(0.0)
+    prev_mc = wb.wb_set_matrix_core_ops(True)
+    try:
+        for on in (True, False):
+            wb.wb_set_matrix_core_ops(on)
+            yu = torch.full((m.u_len,), float("nan"), dtype=torch.float64, device="cuda")
+            yp = torch.full((m.p_len,), float("nan"), dtype=torch.float64, device="cuda")
+            wb.wb_apply_stokes(m, v, dev(u), dev(p), yu, yp)
+            assert _rel(host(yu), wu) < 1e-12, on
+            assert _rel(host(yp), wp) < 1e-12, on
+    finally:
+        wb.wb_set_two_pass_limit(prev_limit)
+        wb.wb_set_matrix_core_ops(prev_mc)
+
+
+@pytest.mark.parametrize("N", [4, 11])
 def test_apply_A_q3_fp32_storage_forms(N):
     # the FP32 precision form at order 3 above the two-pass size: FP32 vectors and coefficient in
     # memory, FP64 arithmetic on the matrix cores (or FP32 line contractions in LDS with the
