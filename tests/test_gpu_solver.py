@@ -604,3 +604,43 @@ def test_solution_matches_oracle_fgmres_at_32cubed_q2():
     # at the paper's tolerance the solution is within 1e-4; driven to 1e-8 it is within 1e-6
     assert max(errs[1e-6][:2]) <= 1e-4
     assert max(errs[1e-8][:2]) <= 1e-6
+
+
+@pytest.mark.parametrize("N", [11, 20])
+def test_matrix_core_levels_match_line_kernels_across_bricks(N):
+    """Order 3 in the brick form on meshes with several bricks in x, y and z (ragged tiles): the
+    V-cycles of A and of both K_w, and the block preconditioner, with the matrix-core level
+    operators (operator, brick-face sums, then the epilogue as its own pass) against the LDS-line
+    kernels with the epilogue fused.  Both are the same operators up to rounding order.  (N = 20
+    coarsens to 5^3; an odd N above 11 would leave a large coarsest level for the host's dense
+    factorization.)"""
+    wb = _wb()
+    w = custom(f"n{N}k3", N, 3, n_sinkers=6, dr=1e6, seed=40 + N)
+    m = wb.Mesh(N, 3)
+    v = wb.Viscosity.sinker(m, w.centers(), w.delta, w.omega, w.mu_min, w.mu_max)
+    ru = random_vector(71, m.u_len)
+    rp = random_vector(72, m.p_len)
+    prev_limit = wb.wb_set_two_pass_limit(0.0)
+    prev_mc = wb.wb_set_matrix_core_ops(True)
+    try:
+        s = wb.Solver(m, v, a_l=w.a_l, a_r=w.a_r, use_graph=0)
+        out = {}
+        for on in (True, False):
+            wb.wb_set_matrix_core_ops(on)
+            za = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+            s.vcycle_A(dev(ru), za)
+            zk = []
+            for side in (0, 1):
+                z = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+                s.vcycle_K(side, dev(rp), z)
+                zk.append(host(z))
+            zu = torch.empty(m.u_len, dtype=torch.float64, device="cuda")
+            zp = torch.empty(m.p_len, dtype=torch.float64, device="cuda")
+            s.precond(dev(ru), dev(rp), zu, zp)
+            out[on] = (host(za), zk[0], zk[1], host(zu), host(zp))
+    finally:
+        wb.wb_set_two_pass_limit(prev_limit)
+        wb.wb_set_matrix_core_ops(prev_mc)
+    for a, b in zip(out[True], out[False]):
+        assert np.all(np.isfinite(a))
+        assert _rel(a, b) < 1e-10
