@@ -345,11 +345,14 @@ WB_API long long wb_profile_summary(char* buf, long long len, int reset);
  * with).  Returns the previous limit. */
 WB_API double wb_set_two_pass_limit(double mb);
 
-/* FP64 order-3 (Q3) brick applies of A and of the scalar Poisson operator (the form above the
- * two-pass limit) run their 1D contractions in x and y on the FP64 matrix cores
- * (v_mfma_f64_4x4x4, on != 0, the default) or as line contractions staged in LDS (on == 0).  The
- * same operator up to rounding order.  Process-wide, for tests and tuning; a captured
- * preconditioner graph keeps the form it was captured with.  Returns the previous setting. */
+/* Order-3 (Q3) brick applies of A and of the scalar Poisson operator (the form above the
+ * two-pass limit; FP64 data, or the FP32 data of the FP32 precision form) run their 1D
+ * contractions in x and y on the FP64 matrix cores (v_mfma_f64_4x4x4, on != 0, the default), with
+ * their Chebyshev and residual updates as a separate streaming pass and the Stokes operator as A,
+ * then B^T added, then B; or as line contractions staged in LDS with the updates and the Stokes
+ * operator fused (on == 0).  The same operators up to rounding order.  Process-wide, for tests and
+ * tuning; a captured preconditioner graph keeps the form it was captured with.  Returns the
+ * previous setting. */
 WB_API int wb_set_matrix_core_ops(int on);
 
 #ifdef __cplusplus
