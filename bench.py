@@ -9,8 +9,9 @@ per second of step time (GDoF/s, whole job; every input resident in HBM).  A ste
 converge stops the benchmark.
 
 Also reported:
-- the A(mu) apply of the workload (100 applies bracketed by HIP events on their stream), its
-  kernels and its roofline (algorithmic bytes, HBM traffic from the committed counter summary);
+- the A(mu) apply of the workload (median of five runs of 100 applies bracketed by HIP events on
+  their stream), its kernels and its roofline (algorithmic bytes, HBM traffic from the committed
+  counter summary), and the rate of a device copy of the velocity vector on the same box;
 - the kernel classes of one eagerly launched step;
 - the precision forms (FP32, BF16x3 on the matrix cores) and the learned coarse correction at the
   workload, each with its error against the FP64 solution and its device memory;
@@ -137,7 +138,8 @@ def main():
     # the A(mu) apply of the workload
     a_apply = measure_a_apply(wb, torch, run.mesh, run.visc())
     log(f"[bench] A apply {w.name}: {a_apply['avg_ms'] * 1e3:.1f} us, {a_apply['gdofs']} GDoF/s, "
-        f"{a_apply['hbm_frac']:.3f} of HBM peak")
+        f"{a_apply['hbm_frac']:.3f} of HBM peak, {a_apply['frac_of_copy']:.3f} of the device copy "
+        f"({a_apply['copy_GBs']:.0f} GB/s)")
 
     if not args.no_forms:
         for name, prec in (("fp32", wb.WB_FP32), ("bf16x3_mfma", wb.WB_BF16)):
@@ -277,15 +279,29 @@ def measure_a_apply(wb, torch, mesh, v, reps=100):
         wb.wb_apply_A(mesh, v, x, y)
     torch.cuda.synchronize()
     # the whole apply (both of its kernels), timed over `reps` back-to-back applies with HIP events
-    # on the stream they are launched on
+    # on the stream they are launched on; the median of five such runs
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    runs = []
+    for _ in range(5):
+        e0.record(st)
+        for _ in range(reps):
+            wb.wb_apply_A(mesh, v, x, y)
+        e1.record(st)
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1) / reps)
+    t_avg = sorted(runs)[len(runs) // 2]
+    # STREAM-copy reference on the same box: a device copy of the velocity vector (read + write)
+    z = torch.empty_like(x)
+    for _ in range(3):
+        z.copy_(x)
     e0.record(st)
     for _ in range(reps):
-        wb.wb_apply_A(mesh, v, x, y)
+        z.copy_(x)
     e1.record(st)
     torch.cuda.synchronize()
-    t_avg = e0.elapsed_time(e1) / reps
+    copy_gbs = 2 * x.numel() * x.element_size() / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del z
     # per-kernel split (each kernel bracketed by its own events, which adds a little per kernel)
     wb.wb_profile_enable(True)
     wb.wb_profile_summary(reset=True)
@@ -306,6 +322,9 @@ def measure_a_apply(wb, torch, mesh, v, reps=100):
             "gdofs": round(mesh.u_len / (t_avg * 1e-3) / 1e9, 3),
             "algorithmic_GBs": round(a_bytes / (t_avg * 1e-3) / 1e9, 1),
             "hbm_frac": round(a_bytes / (t_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "copy_GBs": round(copy_gbs, 1),
+            "frac_of_copy": round(a_bytes / (t_avg * 1e-3) / 1e9 / copy_gbs, 4),
+            "timing": "median of 5 runs of %d back-to-back applies after 10 warm-ups" % reps,
             "bytes_per_launch": a_bytes,
             "traffic_bytes_per_launch": traffic_for(a_key),
             "cache_note": ("working set %.0f MB %s the 256 MB Infinity Cache"
